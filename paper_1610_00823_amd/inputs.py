@@ -1,0 +1,288 @@
+"""Seeded synthetic inputs for the box-code volume potential.
+
+This module is shared by the tests, the benchmark and the CPU oracle's
+callers.  It holds no arithmetic of the volume potential itself: it only
+draws source functions, builds level-restricted quadtrees (the tree is an
+input to the box code, built before it runs, as in the paper's section 3.1
+and section 6.1), and samples the source at each leaf's collocation nodes.
+
+Conventions
+-----------
+* Root box: centre (cx, cy), width ``width``; a box at level l has width
+  ``width * 2**-l`` and integer position (ix, iy), 0 <= ix, iy < 2**l, counted
+  from the lower-left corner of the root.
+* Collocation nodes: first-kind Chebyshev points on [-1, 1],
+  xi_j = -cos((2j+1) pi / (2n)), j = 0..n-1 (increasing), scaled to the box.
+  Samples are stored f[leaf, j2, j1] with the x index (j1) fastest.
+* Refinement (section 3.1 and section 6.1): a box is split while the tail of
+  its Chebyshev coefficients exceeds ``tol`` and its level is below
+  ``max_level``; the tail is the largest |c_ab| with max(a, b) >= n - 2.  For
+  sums of narrow Gaussians a box containing a centre is also split while its
+  width exceeds 4 sigma (a coarse sampling can miss a narrow bump entirely).
+  The tree is then made level-restricted (adjacent leaves, corners included,
+  differ by at most one level).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import numpy as np
+
+
+@dataclass
+class Tree:
+    """A leaf set of a level-restricted quadtree on a square root box."""
+    level: np.ndarray          # int8  [N_L]
+    ix: np.ndarray             # int32 [N_L]
+    iy: np.ndarray             # int32 [N_L]
+    cx: float = 0.0
+    cy: float = 0.0
+    width: float = 1.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_leaves(self) -> int:
+        return int(self.level.shape[0])
+
+    def box_width(self) -> np.ndarray:
+        return self.width * np.ldexp(1.0, -self.level.astype(np.int64))
+
+    def box_centre(self):
+        h = self.box_width()
+        x = self.cx - 0.5 * self.width + (self.ix + 0.5) * h
+        y = self.cy - 0.5 * self.width + (self.iy + 0.5) * h
+        return x, y
+
+
+def cheb1_nodes(n: int) -> np.ndarray:
+    """First-kind Chebyshev points on [-1, 1], increasing."""
+    j = np.arange(n, dtype=np.float64)
+    return -np.cos((2.0 * j + 1.0) * np.pi / (2.0 * n))
+
+
+def node_coords(tree: Tree, n: int):
+    """Physical coordinates of every collocation node, shape [N_L, n, n] (x index fastest)."""
+    xi = cheb1_nodes(n)
+    xc, yc = tree.box_centre()
+    h = tree.box_width()
+    X = xc[:, None, None] + 0.5 * h[:, None, None] * xi[None, None, :]
+    Y = yc[:, None, None] + 0.5 * h[:, None, None] * xi[None, :, None]
+    X = np.broadcast_to(X, (tree.n_leaves, n, n)).copy()
+    Y = np.broadcast_to(Y, (tree.n_leaves, n, n)).copy()
+    return X, Y
+
+
+def sample(tree: Tree, fun: Callable, n: int) -> np.ndarray:
+    """f sampled at every leaf's collocation nodes, float64 [N_L, n, n]."""
+    X, Y = node_coords(tree, n)
+    return np.ascontiguousarray(fun(X, Y), dtype=np.float64)
+
+
+# ---------------------------------------------------------------- sources
+@dataclass
+class GaussianSum:
+    """f(x) = sum_i a_i exp(-|x - c_i|^2 / sigma_i^2)."""
+    a: np.ndarray
+    sigma: np.ndarray
+    c: np.ndarray              # [K, 2]
+
+    def __call__(self, x, y):
+        out = np.zeros(np.broadcast(x, y).shape)
+        for a, s, (c1, c2) in zip(self.a, self.sigma, self.c):
+            out += a * np.exp(-((x - c1) ** 2 + (y - c2) ** 2) / (s * s))
+        return out
+
+
+def centred_gaussian(sigma: float = 0.1) -> GaussianSum:
+    """The single centred Gaussian exp(-|x|^2 / sigma^2)."""
+    return GaussianSum(np.array([1.0]), np.array([sigma]), np.zeros((1, 2)))
+
+
+def random_gaussians(seed: int, K: int = 20, amp=(-1.0, 1.0), log_sigma=(1e-3, 1e-1),
+                     centre=(-0.4, 0.4)) -> GaussianSum:
+    """K Gaussians: amplitudes U(amp), widths log-uniform in log_sigma, centres U(centre)^2.
+
+    Draw order (numpy default_rng(seed), PCG64): a, then sigma, then c.
+    """
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(amp[0], amp[1], K)
+    s = np.exp(rng.uniform(np.log(log_sigma[0]), np.log(log_sigma[1]), K))
+    c = rng.uniform(centre[0], centre[1], (K, 2))
+    return GaussianSum(a, s, c)
+
+
+def kink_source(x, y):
+    """C^0 source with a kink across the curve r = 0.3 + 0.05 cos(5 theta).
+
+    phi = r - (0.3 + 0.05 cos 5 theta); f = sin(4 pi x) cos(4 pi y) inside
+    (phi < 0) and the same times exp(-20 phi) outside: continuous, kinked.
+    """
+    r = np.hypot(x, y)
+    th = np.arctan2(y, x)
+    phi = r - (0.3 + 0.05 * np.cos(5.0 * th))
+    base = np.sin(4.0 * np.pi * x) * np.cos(4.0 * np.pi * y)
+    return np.where(phi < 0.0, base, base * np.exp(-20.0 * np.minimum(np.maximum(phi, 0.0), 50.0)))
+
+
+# ---------------------------------------------------------------- trees
+def uniform_tree(depth: int, cx=0.0, cy=0.0, width=1.0) -> Tree:
+    m = 1 << depth
+    iy, ix = np.meshgrid(np.arange(m, dtype=np.int32), np.arange(m, dtype=np.int32), indexing="ij")
+    # Morton order is not required: any leaf order is accepted by the library.
+    return Tree(np.full(m * m, depth, np.int8), ix.ravel().copy(), iy.ravel().copy(), cx, cy, width,
+                {"kind": "uniform", "depth": depth})
+
+
+def _cheb_tail(vals: np.ndarray, n: int) -> np.ndarray:
+    """Largest |c_ab| with max(a,b) >= n-2 of the tensor interpolants of vals[B, n, n]."""
+    j = np.arange(n)
+    theta = (2.0 * (n - 1 - j) + 1.0) * np.pi / (2.0 * n)     # xi_j = cos(theta_j)
+    a = np.arange(n)
+    T = np.cos(a[:, None] * theta[None, :])                    # T[a, j] = T_a(xi_j)
+    wgt = np.where(a == 0, 1.0, 2.0) / n
+    Tm = T * wgt[:, None]
+    C = np.einsum("aj,bk,ikj->iba", Tm, Tm, vals, optimize=True)   # C[i, b, a]: b along y, a along x
+    mask = np.zeros((n, n), bool)
+    mask[n - 2:, :] = True
+    mask[:, n - 2:] = True
+    return np.abs(C[:, mask]).max(axis=1) if vals.shape[0] else np.zeros(0)
+
+
+def balance(level, ix, iy):
+    """Make a leaf set level-restricted (corner adjacency) by splitting coarse leaves."""
+    leaves = {(int(l), int(x), int(y)) for l, x, y in zip(level, ix, iy)}
+    boxes = set()
+    for (l, x, y) in leaves:
+        while True:
+            boxes.add((l, x, y))
+            if l == 0:
+                break
+            l, x, y = l - 1, x >> 1, y >> 1
+    maxl = max(l for l, _, _ in leaves)
+    by_level = {l: [] for l in range(maxl + 1)}
+    for b in leaves:
+        by_level[b[0]].append(b)
+
+    def split(b):
+        l, x, y = b
+        leaves.discard(b)
+        for cy in (0, 1):
+            for cx in (0, 1):
+                c = (l + 1, 2 * x + cx, 2 * y + cy)
+                leaves.add(c)
+                boxes.add(c)
+                by_level[l + 1].append(c)
+
+    for l in range(maxl, 1, -1):
+        m = 1 << l
+        for b in list(by_level[l]):
+            if b not in leaves:
+                continue
+            _, x, y = b
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    nx, ny = x + dx, y + dy
+                    if (dx == 0 and dy == 0) or not (0 <= nx < m and 0 <= ny < m):
+                        continue
+                    target = (l - 1, nx >> 1, ny >> 1)
+                    # split the covering leaf until the level l-1 box exists
+                    while target not in boxes:
+                        tl, tx, ty = target
+                        k = 1
+                        anc = (tl - k, tx >> k, ty >> k)
+                        while anc not in boxes:
+                            k += 1
+                            anc = (tl - k, tx >> k, ty >> k)
+                        assert anc in leaves
+                        split(anc)
+    out = sorted(leaves)
+    lv = np.array([b[0] for b in out], np.int8)
+    xs = np.array([b[1] for b in out], np.int32)
+    ys = np.array([b[2] for b in out], np.int32)
+    return lv, xs, ys
+
+
+def adaptive_tree(fun: Callable, n: int, tol: float = 1e-10, max_level: int = 14,
+                  min_level: int = 0, cx=0.0, cy=0.0, width=1.0,
+                  seed_points: Optional[np.ndarray] = None, seed_widths: Optional[np.ndarray] = None,
+                  weight: str = "none") -> Tree:
+    """Top-down refinement with the tail criterion, then 2:1 balance.
+
+    weight='none' compares the tail itself with tol; weight='area' multiplies it
+    by the box area (h^2) and 'side' by the side length, the weighted variants of
+    section 6.1.
+    """
+    xi = cheb1_nodes(n)
+    todo = [(0, 0, 0)]
+    leaves = []
+    n_evals = 0
+    while todo:
+        lv = np.array([b[0] for b in todo], np.int64)
+        bx = np.array([b[1] for b in todo], np.int64)
+        by = np.array([b[2] for b in todo], np.int64)
+        h = width * np.ldexp(1.0, -lv)
+        x0 = cx - 0.5 * width + bx * h
+        y0 = cy - 0.5 * width + by * h
+        X = (x0 + 0.5 * h)[:, None, None] + 0.5 * h[:, None, None] * xi[None, None, :]
+        Y = (y0 + 0.5 * h)[:, None, None] + 0.5 * h[:, None, None] * xi[None, :, None]
+        vals = fun(np.broadcast_to(X, (len(todo), n, n)), np.broadcast_to(Y, (len(todo), n, n)))
+        n_evals += vals.size
+        tail = _cheb_tail(np.asarray(vals, np.float64), n)
+        if weight == "area":
+            tail = tail * h * h
+        elif weight == "side":
+            tail = tail * h
+        split = (tail > tol) | (lv < min_level)
+        if seed_points is not None:
+            for (px, py), s in zip(seed_points, seed_widths):
+                inside = (px >= x0) & (px < x0 + h) & (py >= y0) & (py < y0 + h)
+                split |= inside & (h > 4.0 * s)
+        split &= lv < max_level
+        nxt = []
+        for i, b in enumerate(todo):
+            if split[i]:
+                l, x, y = b
+                nxt += [(l + 1, 2 * x + cxx, 2 * y + cyy) for cyy in (0, 1) for cxx in (0, 1)]
+            else:
+                leaves.append(b)
+        todo = nxt
+    lv, xs, ys = balance([b[0] for b in leaves], [b[1] for b in leaves], [b[2] for b in leaves])
+    return Tree(lv, xs, ys, cx, cy, width,
+                {"kind": "adaptive", "tol": tol, "max_level": max_level, "n": n,
+                 "leaves_before_balance": len(leaves), "f_evals": n_evals})
+
+
+def gaussian_tree(src: GaussianSum, n: int, tol=1e-10, max_level=14) -> Tree:
+    """Adaptive tree for a Gaussian sum, with the narrow-feature seed rule."""
+    return adaptive_tree(src, n, tol, max_level, seed_points=src.c, seed_widths=src.sigma)
+
+
+def point_refined_tree(points, depths, cx=0.0, cy=0.0, width=1.0) -> Tree:
+    """Graded tree: boxes containing points[i] are split down to level depths[i], then balanced."""
+    pts = np.asarray(points, float).reshape(-1, 2)
+    sig = width * np.ldexp(1.0, -np.asarray(depths, np.int64)) / 4.0 * 1.0000001
+    zero = lambda x, y: np.zeros(np.broadcast(x, y).shape)
+    t = adaptive_tree(zero, 2, 1.0, int(max(depths)), cx=cx, cy=cy, width=width,
+                      seed_points=pts, seed_widths=sig)
+    t.meta = {"kind": "graded", "points": pts.tolist(), "depths": list(map(int, depths))}
+    return t
+
+
+def is_balanced(tree: Tree) -> bool:
+    lv, xs, ys = balance(tree.level, tree.ix, tree.iy)
+    return len(lv) == tree.n_leaves
+
+
+def workload(name: str, n: int = 8):
+    """The named synthetic workloads: returns (tree, source function)."""
+    if name == "uniform4_gauss":
+        return uniform_tree(4), centred_gaussian(0.1)
+    if name.startswith("gauss20"):
+        seed = int(name.split("_s")[1]) if "_s" in name else 0
+        src = random_gaussians(seed, 20)
+        return gaussian_tree(src, n, 1e-10, 14), src
+    if name.startswith("kink"):
+        cap = int(name.split("_cap")[1]) if "_cap" in name else 16
+        return adaptive_tree(kink_source, n, 1e-10, cap), kink_source
+    raise KeyError(name)
