@@ -18,10 +18,13 @@
  * This is the plain definition, summed directly over every (target, leaf)
  * pair; no expansions and no tables.
  *
- * Quadrature, per (target x, leaf B of width w, distance d from x to B):
- *   - d >= w/2: tensor Gauss-Legendre q x q on B, q chosen from d/w so that
+ * Quadrature, per (target x, square S of width w -- a leaf or a quarter of one
+ * -- at distance d from x):
+ *   - d >= w/2: tensor Gauss-Legendre q x q on S, q chosen from d/w so that
  *     the Bernstein-ellipse estimate of the error is below 1e-17 relative.
- *   - d <  w/2: polar coordinates about x.  B is the signed sum of the four
+ *   - w/16 <= d < w/2: the four quarters of S, each treated the same way.
+ *   - d < w/16 (x inside S or just outside): polar coordinates about x.  S is
+ *     the signed sum of the four
  *     triangles (x, corner_k, corner_k+1), each parametrised by the angle
  *     from the normal to its edge line (so the ray length p/cos(phi) keeps
  *     full relative precision when x is close to that line).  Along each ray the source is a
@@ -193,14 +196,14 @@ static void adapt(const ray_ctx *c, const gl_t *g, double a, double b, const dou
 /* The square is the signed sum of the triangles (x, A, B) over its
  * counter-clockwise edges A -> B; each triangle is integrated in polar
  * coordinates about x, the angle measured from the normal to the edge line. */
-static void near_leaf(const leaf_t *L, const radial_t *R, const gl_t *g, double x, double y,
-                      double out[3]) {
-  double cx[4] = {L->x0, L->x0 + L->w, L->x0 + L->w, L->x0};
-  double cy[4] = {L->y0, L->y0, L->y0 + L->w, L->y0 + L->w};     /* counter-clockwise */
+static void near_square(const leaf_t *L, const radial_t *R, const gl_t *g, double sx0, double sy0, double sw,
+                        double x, double y, double out[3]) {
+  double cx[4] = {sx0, sx0 + sw, sx0 + sw, sx0};
+  double cy[4] = {sy0, sy0, sy0 + sw, sy0 + sw};     /* counter-clockwise */
   double tol[3];
   double fs = L->fscale > 0.0 ? L->fscale : 1.0;
-  tol[0] = 1e-15 * fs * L->w * L->w * (1.0 + fabs(log(L->w)));
-  tol[1] = tol[2] = 1e-15 * fs * L->w;
+  tol[0] = 1e-15 * fs * sw * sw * (1.0 + fabs(log(sw)));
+  tol[1] = tol[2] = 1e-15 * fs * sw;
   out[0] = out[1] = out[2] = 0.0;
   for (int k = 0; k < 4; ++k) {
     double Ax = cx[k], Ay = cy[k], Bx = cx[(k + 1) & 3], By = cy[(k + 1) & 3];
@@ -208,7 +211,7 @@ static void near_leaf(const leaf_t *L, const radial_t *R, const gl_t *g, double 
     double ex = (Bx - Ax) / el, ey = (By - Ay) / el;     /* exact for axis-aligned edges */
     double nx = ey, ny = -ex;                           /* outward normal */
     double ps = (Ax - x) * nx + (Ay - y) * ny;          /* signed distance to the edge line */
-    if (fabs(ps) < 1e-15 * L->w) continue;              /* degenerate triangle: zero area */
+    if (fabs(ps) < 1e-15 * sw) continue;                /* degenerate triangle: zero area */
     double sg = ps > 0.0 ? 1.0 : -1.0;
     double tA = (Ax - x) * ex + (Ay - y) * ey, tB = (Bx - x) * ex + (By - y) * ey;
     ray_ctx c = {L, R, x, y, fabs(ps), sg * nx, sg * ny, ex, ey};
@@ -221,10 +224,16 @@ static void near_leaf(const leaf_t *L, const radial_t *R, const gl_t *g, double 
 }
 
 /* ------------------------------------------------------------- far field */
-static void far_leaf(const leaf_t *L, const gl_t *g, double x, double y, double out[3]) {
+static void far_square(const leaf_t *L, const gl_t *g, double sx0, double sy0, double sw, double x, double y,
+                       double out[3]) {
   int n = L->n, q = g->q;
-  double Tq[OR_MAXQ][OR_MAXN], Gm[OR_MAXN][OR_MAXQ];
-  for (int a = 0; a < q; ++a) cheb_values(n, g->x[a], Tq[a]);
+  double Tq[OR_MAXQ][OR_MAXN], Ty[OR_MAXQ][OR_MAXN], Gm[OR_MAXN][OR_MAXQ];
+  double r = 0.5 * sw, xc = sx0 + r, yc = sy0 + r;
+  /* Chebyshev values at the Gauss points of the square, in the leaf's coordinates */
+  for (int a = 0; a < q; ++a) {
+    cheb_values(n, 2.0 * (xc + r * g->x[a] - L->x0) / L->w - 1.0, Tq[a]);
+    cheb_values(n, 2.0 * (yc + r * g->x[a] - L->y0) / L->w - 1.0, Ty[a]);
+  }
   /* Gm[b][a] = sum_i c[b][i] T_i(x_a) */
   for (int b = 0; b < n; ++b)
     for (int a = 0; a < q; ++a) {
@@ -232,13 +241,12 @@ static void far_leaf(const leaf_t *L, const gl_t *g, double x, double y, double 
       for (int i = 0; i < n; ++i) s += L->coef[b * n + i] * Tq[a][i];
       Gm[b][a] = s;
     }
-  double r = 0.5 * L->w, xc = L->x0 + r, yc = L->y0 + r;
   double sv = 0.0, sx = 0.0, sy = 0.0;
   for (int bb = 0; bb < q; ++bb) {
     double yy = yc + r * g->x[bb];
     for (int a = 0; a < q; ++a) {
       double fv = 0.0;
-      for (int b = 0; b < n; ++b) fv += Gm[b][a] * Tq[bb][b];
+      for (int b = 0; b < n; ++b) fv += Gm[b][a] * Ty[bb][b];
       double xx = xc + r * g->x[a];
       double dx = x - xx, dy = y - yy, r2 = dx * dx + dy * dy;
       double wt = g->w[a] * g->w[bb] * fv;
@@ -261,11 +269,33 @@ static int far_order(int n, double d, double w) {
   return q;
 }
 
-static double box_dist(const leaf_t *L, double x, double y) {
+static double sq_dist(double sx0, double sy0, double sw, double x, double y) {
   double dx = 0.0, dy = 0.0;
-  if (x < L->x0) dx = L->x0 - x; else if (x > L->x0 + L->w) dx = x - L->x0 - L->w;
-  if (y < L->y0) dy = L->y0 - y; else if (y > L->y0 + L->w) dy = y - L->y0 - L->w;
+  if (x < sx0) dx = sx0 - x; else if (x > sx0 + sw) dx = x - sx0 - sw;
+  if (y < sy0) dy = sy0 - y; else if (y > sy0 + sw) dy = y - sy0 - sw;
   return hypot(dx, dy);
+}
+
+/* Integral over the square [sx0, sx0+sw] x [sy0, sy0+sw] (part of leaf L):
+ * tensor rule when the target is at least sw/2 away; polar when it lies inside
+ * or within sw/16 (the signed triangles then nearly do not cancel); otherwise
+ * the four quarters, so that a target outside the square never meets the large
+ * cancelling triangles of a distant polar decomposition. */
+static void square(const leaf_t *L, const radial_t *R, const gl_t *gth, const gl_t *rules, double sx0,
+                   double sy0, double sw, double x, double y, double out[3]) {
+  double d = sq_dist(sx0, sy0, sw, x, y);
+  if (d >= 0.5 * sw) {
+    far_square(L, &rules[far_order(L->n, d, sw)], sx0, sy0, sw, x, y, out);
+  } else if (d < sw / 16.0) {
+    near_square(L, R, gth, sx0, sy0, sw, x, y, out);
+  } else {
+    double h = 0.5 * sw, o[3];
+    out[0] = out[1] = out[2] = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      square(L, R, gth, rules, sx0 + (k & 1) * h, sy0 + (k >> 1) * h, h, x, y, o);
+      out[0] += o[0]; out[1] += o[1]; out[2] += o[2];
+    }
+  }
 }
 
 /* ------------------------------------------------------------------- API */
@@ -315,9 +345,7 @@ int oracle_volume(int n, double cx, double cy, double width, int nleaf, const in
     double x = tx[t], y = ty[t], sv = 0.0, sx = 0.0, sy = 0.0, o[3];
     for (int i = 0; i < nleaf; ++i) {
       if (use && !use[i]) continue;
-      double d = box_dist(&L[i], x, y);
-      if (d < 0.5 * L[i].w) near_leaf(&L[i], &R, &gth, x, y, o);
-      else far_leaf(&L[i], &rules[far_order(n, d, L[i].w)], x, y, o);
+      square(&L[i], &R, &gth, rules, L[i].x0, L[i].y0, L[i].w, x, y, o);
       sv += o[0]; sx += o[1]; sy += o[2];
     }
     V[t] = sv; Gx[t] = sx; Gy[t] = sy;
