@@ -1,0 +1,170 @@
+/*
+ * boxfmm.h -- C ABI of the MI355X box-code volume potential library.
+ *
+ * The library evaluates, at every collocation node of a level-restricted
+ * quadtree, the volume potential of the piecewise polynomial source and its
+ * gradient (section 3, eq. volumeint3; gradient by the second volume
+ * integral of section 3.2, eq. volumeint3x):
+ *
+ *     V(x) = int_Box G(x - y) f~(y) dy,   grad V(x) = int_Box grad_x G(x - y) f~(y) dy,
+ *     G(r) = log|r| / (2 pi),
+ *
+ * where f~ is, on each leaf, the degree-(n-1) tensor polynomial through the
+ * leaf's samples at first-kind Chebyshev nodes (section 3.1).  As in the box
+ * code of section 3.1, far interactions go through multipole and local
+ * expansions and near ones through precomputed tables for a unit box,
+ * scaled per level (section 3.1, last paragraph).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: BX_OK (0) on success, a negative BX_E_* code otherwise.
+ *   bx_last_error() gives a message for the calling thread's last failure.
+ *   No C++ exception crosses this interface.
+ * - Nodes: xi_j = -cos((2j+1) pi / 2n), j = 0..n-1, on [-1,1], scaled to
+ *   each leaf.  A leaf's n*n samples are stored with the x index fastest.
+ * - Device buffers (f, V, G) are owned by the caller, allocated on the
+ *   context's device, contiguous, 8-byte aligned FP64.  The library reads f
+ *   and writes V, G inside the call's stream order and keeps no reference
+ *   after the call returns.
+ * - Layouts: f[n_rhs][n_leaves][n][n], V[n_rhs][n_leaves][n][n],
+ *   G[n_rhs][n_leaves][2][n][n] (component 0 = dV/dx1, 1 = dV/dx2).  Leaf
+ *   order is the order of the tree descriptor.
+ * - Calls that take a stream enqueue work on it and return without
+ *   synchronising; the caller synchronises.  A NULL stream is the default
+ *   stream.
+ * - Objects: bx_ctx and bx_tree are opaque and owned by the library; free
+ *   them with bx_destroy / bx_tree_destroy.  A tree may only be used with
+ *   the context that created it.  Concurrent calls on one context from
+ *   several threads are not supported.
+ */
+#ifndef BOXFMM_H
+#define BOXFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bx_ctx bx_ctx;
+typedef struct bx_tree bx_tree;
+typedef void *bx_stream_t;   /* a hipStream_t */
+
+enum {
+  BX_OK = 0,
+  BX_E_ARG = -1,            /* null or inconsistent argument */
+  BX_E_NOT_BALANCED = -2,   /* adjacent leaves (corners included) differ by more than one level */
+  BX_E_INVALID_TREE = -3,   /* leaves overlap, repeat, fall outside the root or leave holes */
+  BX_E_UNSUPPORTED = -4,    /* node count or expansion order outside the supported set */
+  BX_E_HIP = -5,            /* a HIP runtime call failed */
+  BX_E_OOM = -6,            /* device or host allocation failed */
+  BX_E_NO_TABLES = -7       /* evaluation before bx_build_tables */
+};
+
+/* Precision of the near-field table products. */
+enum {
+  BX_FP64 = 0,              /* FP64 MFMA throughout */
+  BX_SPLIT_BF16 = 1,        /* near tables as exact BF16 slice products with FP32 accumulation,
+                               recombined in FP64 (far field, log terms and sums stay FP64) */
+  BX_HOST_ONLY = 0x100      /* or-ed in: no device is touched; tables and trees are built on the
+                               host for inspection only and evaluation returns BX_E_UNSUPPORTED */
+};
+
+/*
+ * Create a context on the current HIP device.
+ *   n_nodes: collocation nodes per side, one of 4, 8, 16.
+ *   p_exp:   expansion order p (coefficients 0..p), 8 <= p <= 47.
+ *   flags:   BX_FP64 or BX_SPLIT_BF16, optionally or-ed with BX_HOST_ONLY.
+ * Errors: BX_E_ARG (out NULL), BX_E_UNSUPPORTED, BX_E_HIP.
+ */
+int bx_create(bx_ctx **out, int n_nodes, int p_exp, uint32_t flags);
+
+/*
+ * Build the unit-box operators on the host in FP64 and upload them: the
+ * near-field tables for the 33 neighbour configurations of a level-restricted
+ * tree (section 3.1: a finite set of near interactions up to scale), for V and
+ * both gradient components, and the expansion operators.  Blocks the calling
+ * thread.  quad_tol <= 0 selects the default (1e-15).  cache_dir may be NULL;
+ * if given, tables are read from / written to a file keyed by (n, p) there and
+ * rebuilt when the file is missing or fails its checksum.
+ * Errors: BX_E_ARG, BX_E_HIP, BX_E_OOM.
+ */
+int bx_build_tables(bx_ctx *ctx, double quad_tol, const char *cache_dir);
+
+/* Host description of one tree: the root box and its leaves (copied by upload). */
+typedef struct {
+  double cx, cy, width;     /* root box centre and width */
+  int32_t n_leaves;
+  const int8_t *level;      /* [n_leaves], 0 = root, at most 29 */
+  const int32_t *ix;        /* [n_leaves], 0 <= ix < 2^level, from the left edge */
+  const int32_t *iy;        /* [n_leaves], 0 <= iy < 2^level, from the bottom edge */
+} bx_tree_desc;
+
+/*
+ * Validate a leaf set (it must tile the root exactly and be level-restricted,
+ * section 3.1), build the box hierarchy and the interaction lists on the host,
+ * and upload them.  Only n_trees == 1 is accepted.  The stream orders the
+ * uploads.  Errors: BX_E_ARG, BX_E_INVALID_TREE, BX_E_NOT_BALANCED, BX_E_HIP,
+ * BX_E_OOM.
+ */
+int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree **out,
+                   bx_stream_t stream);
+
+/* V and grad V at every node of every leaf, for n_rhs right-hand sides. */
+int bx_volume_eval_grad(bx_ctx *ctx, const bx_tree *tree, const double *f_dev, int n_rhs,
+                        double *V_dev, double *G_dev, bx_stream_t stream);
+
+/* V only (the gradient is still formed internally and discarded). */
+int bx_volume_eval(bx_ctx *ctx, const bx_tree *tree, const double *f_dev, int n_rhs,
+                   double *V_dev, bx_stream_t stream);
+
+/* grad V only. */
+int bx_volume_grad(bx_ctx *ctx, const bx_tree *tree, const double *f_dev, int n_rhs,
+                   double *G_dev, bx_stream_t stream);
+
+/* Quantities for reports, written to *out (host). */
+enum {
+  BX_Q_N_LEAVES = 0, BX_Q_N_BOXES = 1, BX_Q_N_LEVELS = 2, BX_Q_NODES = 3, BX_Q_ORDER = 4,
+  BX_Q_NEAR_PAIRS = 5,       /* U-list (target, source) pairs */
+  BX_Q_V_PAIRS = 6,          /* V-list pairs (M2L) */
+  BX_Q_W_PAIRS = 7,          /* W-list pairs (multipole to targets) */
+  BX_Q_X_PAIRS = 8,          /* X-list pairs (sources to local) */
+  BX_Q_NEAR_FLOPS = 9,       /* algorithmic FP64 flops of the near-table products, one RHS */
+  BX_Q_FAR_FLOPS = 10,       /* algorithmic flops of P2M, M2M, M2L, W, X, L2L, L2T, one RHS */
+  BX_Q_NEAR_TILES = 11,      /* 16-target tiles of the near kernel */
+  BX_Q_NEAR_SLOTS = 12,      /* (tile, configuration) slots of the near kernel */
+  BX_Q_UPLOAD_MS = 13        /* host time of the last bx_tree_upload, milliseconds */
+};
+int bx_query(const bx_ctx *ctx, const bx_tree *tree, int what, double *out);
+
+/*
+ * Copy one host-side interaction list of a tree, for checks of the list
+ * builder.  kind: 0 = U (target leaf, source leaf, config), 1 = V (target box,
+ * source box, offset class), 2 = W (target leaf, source box, config),
+ * 3 = X (target box, source leaf, config); boxes are given as
+ * (level << 58 | ix << 29 | iy) keys, leaves by descriptor index.  With
+ * out == NULL only *count is written; otherwise up to cap triples
+ * (int64 each) are copied.
+ */
+int bx_tree_list(const bx_tree *tree, int kind, int64_t *out, int64_t cap, int64_t *count);
+
+/*
+ * Copy one of the context's host FP64 operator tables (after bx_build_tables),
+ * for checks of the table builder.  which: 0 near tables [33][MR][P] (rows:
+ * V for the P targets, dV/dx1, dV/dx2, then the mass row, zero padding to MR,
+ * a multiple of 16), 1 P2M [2 KP][P], 2 M2M [4][p+1][p+1][2], 3 L2L
+ * [4][p+1][p+1][2], 4 M2L core [KP][KP], 5 M2L source powers [49][KP][2],
+ * 6 M2L target powers [49][KP][2], 7 log|d| [49], 8 L2T [3P][2 KP],
+ * 9 M2T [20][3P][2 KP], 10 P2L [20][2 KP][P], 11 unit-box weights [P];
+ * KP = p+1 rounded up to 16.  With out == NULL only *count is written.
+ */
+int bx_table_copy(const bx_ctx *ctx, int which, double *out, int64_t cap, int64_t *count);
+
+void bx_tree_destroy(bx_tree *tree);
+void bx_destroy(bx_ctx *ctx);
+const char *bx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BOXFMM_H */

@@ -1,0 +1,213 @@
+"""Thin Python binding of libboxfmm.so (argument marshalling only).
+
+Every step of the evaluation runs in the library's HIP kernels; torch is used
+for device memory and streams.  Importing this module does not load the
+library; the first call does, and raises if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libboxfmm.so")
+
+BX_OK = 0
+BX_E_ARG, BX_E_NOT_BALANCED, BX_E_INVALID_TREE, BX_E_UNSUPPORTED, BX_E_HIP, BX_E_OOM, BX_E_NO_TABLES = (
+    -1, -2, -3, -4, -5, -6, -7)
+BX_FP64, BX_SPLIT_BF16, BX_HOST_ONLY = 0, 1, 0x100
+Q = dict(n_leaves=0, n_boxes=1, n_levels=2, nodes=3, order=4, near_pairs=5, v_pairs=6, w_pairs=7,
+         x_pairs=8, near_flops=9, far_flops=10, near_tiles=11, near_slots=12, upload_ms=13)
+TABLES = dict(near=0, p2m=1, m2m=2, l2l=3, m2l_core=4, m2l_src_pow=5, m2l_tgt_pow=6, logd=7, l2t=8,
+              m2t=9, p2l=10, weights=11)
+SYMBOLS = ["bx_create", "bx_build_tables", "bx_tree_upload", "bx_volume_eval_grad", "bx_volume_eval",
+           "bx_volume_grad", "bx_query", "bx_tree_list", "bx_table_copy", "bx_tree_destroy",
+           "bx_destroy", "bx_last_error"]
+
+_lib = None
+
+
+class BoxFMMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"boxfmm error {code}: {msg}")
+        self.code = code
+
+
+class _TreeDesc(ctypes.Structure):
+    _fields_ = [("cx", ctypes.c_double), ("cy", ctypes.c_double), ("width", ctypes.c_double),
+                ("n_leaves", ctypes.c_int32), ("level", ctypes.c_void_p), ("ix", ctypes.c_void_p),
+                ("iy", ctypes.c_void_p)]
+
+
+def lib():
+    """Load libboxfmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1610_00823_amd.build_lib.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32, i64, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_int64, ctypes.c_double
+        L.bx_create.argtypes = [ctypes.POINTER(vp), i32, i32, u32]
+        L.bx_build_tables.argtypes = [vp, dp, ctypes.c_char_p]
+        L.bx_tree_upload.argtypes = [vp, ctypes.POINTER(_TreeDesc), i32, ctypes.POINTER(vp), vp]
+        L.bx_volume_eval_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.bx_volume_eval.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.bx_volume_grad.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.bx_query.argtypes = [vp, vp, i32, ctypes.POINTER(dp)]
+        L.bx_tree_list.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
+        L.bx_table_copy.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
+        L.bx_tree_destroy.argtypes = [vp]
+        L.bx_destroy.argtypes = [vp]
+        L.bx_last_error.restype = ctypes.c_char_p
+        for name in SYMBOLS:
+            if name not in ("bx_tree_destroy", "bx_destroy", "bx_last_error"):
+                getattr(L, name).restype = i32
+        L.bx_tree_destroy.restype = None
+        L.bx_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != BX_OK:
+        raise BoxFMMError(rc, lib().bx_last_error().decode())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Context:
+    """bx_create + bx_build_tables."""
+
+    def __init__(self, n: int = 8, p: int = 30, flags: int = BX_FP64, cache_dir=None, quad_tol: float = 0.0,
+                 build: bool = True):
+        self._h = ctypes.c_void_p()
+        _check(lib().bx_create(ctypes.byref(self._h), int(n), int(p), int(flags)))
+        self.n, self.p, self.flags = n, p, flags
+        if build:
+            self.build_tables(quad_tol, cache_dir)
+
+    def build_tables(self, quad_tol=0.0, cache_dir=None):
+        cd = cache_dir.encode() if cache_dir else None
+        _check(lib().bx_build_tables(self._h, float(quad_tol), cd))
+
+    def table(self, name: str) -> np.ndarray:
+        cnt = ctypes.c_int64()
+        _check(lib().bx_table_copy(self._h, TABLES[name], None, 0, ctypes.byref(cnt)))
+        out = np.zeros(cnt.value)
+        _check(lib().bx_table_copy(self._h, TABLES[name], out.ctypes.data, cnt.value, ctypes.byref(cnt)))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().bx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree:
+    """bx_tree_upload of one leaf set (level, ix, iy arrays) on a root box."""
+
+    def __init__(self, ctx: Context, level, ix, iy, cx=0.0, cy=0.0, width=1.0, stream=None):
+        self.ctx = ctx
+        self._lv = np.ascontiguousarray(level, np.int8)
+        self._ix = np.ascontiguousarray(ix, np.int32)
+        self._iy = np.ascontiguousarray(iy, np.int32)
+        d = _TreeDesc(float(cx), float(cy), float(width), int(self._lv.size), self._lv.ctypes.data,
+                      self._ix.ctypes.data, self._iy.ctypes.data)
+        self._h = ctypes.c_void_p()
+        _check(lib().bx_tree_upload(ctx._h, ctypes.byref(d), 1, ctypes.byref(self._h), _stream_ptr(stream)))
+        self.n_leaves = int(self._lv.size)
+
+    @classmethod
+    def from_inputs(cls, ctx, tree, stream=None):
+        return cls(ctx, tree.level, tree.ix, tree.iy, tree.cx, tree.cy, tree.width, stream)
+
+    def query(self, what: str) -> float:
+        v = ctypes.c_double()
+        _check(lib().bx_query(self.ctx._h, self._h, Q[what], ctypes.byref(v)))
+        return v.value
+
+    def lists(self, kind: int) -> np.ndarray:
+        cnt = ctypes.c_int64()
+        _check(lib().bx_tree_list(self._h, int(kind), None, 0, ctypes.byref(cnt)))
+        out = np.zeros((cnt.value, 3), np.int64)
+        _check(lib().bx_tree_list(self._h, int(kind), out.ctypes.data, cnt.value, ctypes.byref(cnt)))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().bx_tree_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dev_check(t, shape, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 tensor on the GPU")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def volume_eval_grad(ctx: Context, tree: Tree, f, V=None, G=None, stream=None):
+    """V[n_rhs, N_L, n, n] and G[n_rhs, N_L, 2, n, n] for f[n_rhs, N_L, n, n] (torch, on the GPU)."""
+    import torch
+    if f.dim() == 3:
+        f = f.unsqueeze(0)
+    nrhs, n = f.shape[0], ctx.n
+    _dev_check(f, (nrhs, tree.n_leaves, n, n), "f")
+    if V is None:
+        V = torch.empty_like(f)
+    if G is None:
+        G = torch.empty((nrhs, tree.n_leaves, 2, n, n), dtype=f.dtype, device=f.device)
+    _dev_check(V, (nrhs, tree.n_leaves, n, n), "V")
+    _dev_check(G, (nrhs, tree.n_leaves, 2, n, n), "G")
+    if stream is None:
+        stream = torch.cuda.current_stream(f.device)
+    _check(lib().bx_volume_eval_grad(ctx._h, tree._h, ctypes.c_void_p(f.data_ptr()), int(nrhs),
+                                     ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(G.data_ptr()),
+                                     _stream_ptr(stream)))
+    return V, G
+
+
+def volume_eval(ctx, tree, f, V=None, stream=None):
+    import torch
+    if f.dim() == 3:
+        f = f.unsqueeze(0)
+    _dev_check(f, (f.shape[0], tree.n_leaves, ctx.n, ctx.n), "f")
+    V = torch.empty_like(f) if V is None else V
+    _dev_check(V, tuple(f.shape), "V")
+    stream = torch.cuda.current_stream(f.device) if stream is None else stream
+    _check(lib().bx_volume_eval(ctx._h, tree._h, ctypes.c_void_p(f.data_ptr()), int(f.shape[0]),
+                                ctypes.c_void_p(V.data_ptr()), _stream_ptr(stream)))
+    return V
+
+
+def volume_grad(ctx, tree, f, G=None, stream=None):
+    import torch
+    if f.dim() == 3:
+        f = f.unsqueeze(0)
+    nrhs, n = f.shape[0], ctx.n
+    _dev_check(f, (nrhs, tree.n_leaves, n, n), "f")
+    G = torch.empty((nrhs, tree.n_leaves, 2, n, n), dtype=f.dtype, device=f.device) if G is None else G
+    _dev_check(G, (nrhs, tree.n_leaves, 2, n, n), "G")
+    stream = torch.cuda.current_stream(f.device) if stream is None else stream
+    _check(lib().bx_volume_grad(ctx._h, tree._h, ctypes.c_void_p(f.data_ptr()), int(nrhs),
+                                ctypes.c_void_p(G.data_ptr()), _stream_ptr(stream)))
+    return G

@@ -1,0 +1,410 @@
+// C ABI of the box-code library: contexts, table build/upload, tree upload
+// and the stream-ordered evaluation of V and grad V.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bx_internal.h"
+#include "kernels.h"
+
+struct bx_ctx {
+  int n = 0, p = 0, device = 0;
+  uint32_t flags = 0;
+  bool ready = false;
+  bx::Tables T;
+  std::vector<void *> dev;    // device allocations owned by the context
+  bx::DevTables dt{};
+};
+
+struct bx_tree {
+  bx_ctx *ctx = nullptr;
+  bx::HostTree H;
+  std::vector<void *> dev;
+  bx::DevTree dg{};
+  double *M = nullptr, *L = nullptr;   // expansions, grown with n_rhs
+  int exp_rhs = 0;
+  double upload_ms = 0.0;
+  int64_t n_slots = 0;
+};
+
+namespace bx {
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(BX_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class Tv>
+int upload(std::vector<void *> &owned, const std::vector<Tv> &h, const Tv **out, hipStream_t s) {
+  *out = nullptr;
+  if (h.empty()) {  // keep a valid pointer for empty lists
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, 16);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(BX_E_OOM, "hipMalloc") : hip_fail(e, "hipMalloc");
+    owned.push_back(p);
+    *out = (const Tv *)p;
+    return BX_OK;
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, h.size() * sizeof(Tv));
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(BX_E_OOM, "hipMalloc") : hip_fail(e, "hipMalloc");
+  owned.push_back(p);
+  e = hipMemcpyAsync(p, h.data(), h.size() * sizeof(Tv), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  *out = (const Tv *)p;
+  return BX_OK;
+}
+
+// CSR by target from (target, source, config) triples.
+void csr(int ntgt, const std::vector<int> &t, const std::vector<int> &s, const std::vector<int> &c,
+         std::vector<int> &ptr, std::vector<int> &src, std::vector<int> &cfg) {
+  ptr.assign(ntgt + 1, 0);
+  for (int x : t) ptr[x + 1]++;
+  for (int i = 0; i < ntgt; ++i) ptr[i + 1] += ptr[i];
+  std::vector<int> pos(ptr.begin(), ptr.end() - 1);
+  src.resize(t.size());
+  cfg.resize(t.size());
+  for (size_t i = 0; i < t.size(); ++i) {
+    int k = pos[t[i]]++;
+    src[k] = s[i];
+    cfg[k] = c[i];
+  }
+}
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+}  // namespace bx
+
+using namespace bx;
+
+extern "C" {
+
+const char *bx_last_error(void) { return g_err.c_str(); }
+
+int bx_create(bx_ctx **out, int n_nodes, int p_exp, uint32_t flags) {
+  if (!out) return fail(BX_E_ARG, "bx_create: out is NULL");
+  *out = nullptr;
+  if (n_nodes != 4 && n_nodes != 8 && n_nodes != 16) return fail(BX_E_UNSUPPORTED, "bx_create: n must be 4, 8 or 16");
+  if (p_exp < 8 || p_exp > 47) return fail(BX_E_UNSUPPORTED, "bx_create: p must be in 8..47");
+  uint32_t prec = flags & ~(uint32_t)BX_HOST_ONLY;
+  if (prec != BX_FP64 && prec != BX_SPLIT_BF16) return fail(BX_E_UNSUPPORTED, "bx_create: unknown flags");
+  int dev = 0;
+  if (!(flags & BX_HOST_ONLY)) {
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  }
+  bx_ctx *c = new (std::nothrow) bx_ctx;
+  if (!c) return fail(BX_E_OOM, "bx_create");
+  c->n = n_nodes;
+  c->p = p_exp;
+  c->flags = flags;
+  c->device = dev;
+  *out = c;
+  return BX_OK;
+}
+
+int bx_build_tables(bx_ctx *ctx, double quad_tol, const char *cache_dir) {
+  if (!ctx) return fail(BX_E_ARG, "bx_build_tables: ctx is NULL");
+  double tol = quad_tol > 0 ? quad_tol : 1e-15;
+  Tables &T = ctx->T;
+  bool loaded = false;
+  std::string path;
+  if (cache_dir && *cache_dir) {
+    char name[128];
+    std::snprintf(name, sizeof name, "/boxfmm_tables_n%d_p%d.bin", ctx->n, ctx->p);
+    path = std::string(cache_dir) + name;
+    loaded = load_tables(T, path, ctx->n, ctx->p);
+  }
+  if (!loaded) {
+    int rc = build_tables(T, ctx->n, ctx->p, tol, 0);
+    if (rc) return fail(rc, "bx_build_tables: table construction failed");
+    if (!path.empty()) save_tables(T, path);   // a failed cache write is not an error
+  }
+  if (ctx->flags & BX_HOST_ONLY) {
+    ctx->ready = true;
+    return BX_OK;
+  }
+  for (void *p : ctx->dev) (void)hipFree(p);
+  ctx->dev.clear();
+  DevTables &d = ctx->dt;
+  d.n = T.n; d.P = T.P; d.p = T.p; d.nt = T.nt; d.KP = T.KP; d.MR = T.MR;
+  hipStream_t s = nullptr;
+  int rc = 0;
+  if ((rc = upload(ctx->dev, T.wq, &d.wq, s)) || (rc = upload(ctx->dev, T.near_, &d.near_, s)) ||
+      (rc = upload(ctx->dev, T.p2m, &d.p2m, s)) || (rc = upload(ctx->dev, T.m2m, &d.m2m, s)) ||
+      (rc = upload(ctx->dev, T.l2l, &d.l2l, s)) || (rc = upload(ctx->dev, T.H, &d.H, s)) ||
+      (rc = upload(ctx->dev, T.pw_src, &d.pw_src, s)) || (rc = upload(ctx->dev, T.pw_tgt, &d.pw_tgt, s)) ||
+      (rc = upload(ctx->dev, T.logd, &d.logd, s)) || (rc = upload(ctx->dev, T.l2t, &d.l2t, s)) ||
+      (rc = upload(ctx->dev, T.m2t, &d.m2t, s)) || (rc = upload(ctx->dev, T.p2l, &d.p2l, s)))
+    return rc;
+  d.near_frag = nullptr;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "bx_build_tables: upload");
+  ctx->ready = true;
+  return BX_OK;
+}
+
+int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree **out, bx_stream_t stream) {
+  if (!ctx || !trees || !out) return fail(BX_E_ARG, "bx_tree_upload: NULL argument");
+  *out = nullptr;
+  if (n_trees != 1) return fail(BX_E_UNSUPPORTED, "bx_tree_upload: one tree per call");
+  auto t0 = std::chrono::steady_clock::now();
+  bx_tree *t = new (std::nothrow) bx_tree;
+  if (!t) return fail(BX_E_OOM, "bx_tree_upload");
+  t->ctx = ctx;
+  std::string err;
+  int rc = build_tree(t->H, trees[0], err);
+  if (rc) {
+    delete t;
+    return fail(rc, "bx_tree_upload: " + err);
+  }
+  HostTree &H = t->H;
+  hipStream_t s = (hipStream_t)stream;
+  DevTree &g = t->dg;
+  g.n_leaves = H.n_leaves; g.n_boxes = H.n_boxes; g.n_levels = H.n_levels; g.width = H.width;
+  std::vector<int> leaf_level(H.n_leaves);
+  for (int i = 0; i < H.n_leaves; ++i) leaf_level[i] = H.lvl[H.box_of_leaf[i]];
+  std::vector<int> up, us, uc, vp, vs, vc, wp, ws, wc, xp, xs, xc;
+  csr(H.n_leaves, H.u_t, H.u_s, H.u_c, up, us, uc);
+  csr(H.n_boxes, H.v_t, H.v_s, H.v_c, vp, vs, vc);
+  csr(H.n_leaves, H.w_t, H.w_s, H.w_c, wp, ws, wc);
+  csr(H.n_boxes, H.x_t, H.x_s, H.x_c, xp, xs, xc);
+  // near tiles: leaves sorted by their set of configurations, 16 per tile
+  std::vector<uint64_t> sig(H.n_leaves, 0);
+  for (int i = 0; i < H.n_leaves; ++i)
+    for (int e = up[i]; e < up[i + 1]; ++e) sig[i] |= 1ull << uc[e];
+  std::vector<int> order(H.n_leaves);
+  for (int i = 0; i < H.n_leaves; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sig[a] < sig[b]; });
+  int ntiles = (H.n_leaves + 15) / 16;
+  std::vector<int> tile_tgt((size_t)ntiles * 16, -1), tile_ptr(ntiles + 1, 0), slot_cfg, slot_src;
+  for (int tt = 0; tt < ntiles; ++tt) {
+    uint64_t uni = 0;
+    for (int k = 0; k < 16 && tt * 16 + k < H.n_leaves; ++k) {
+      int leaf = order[tt * 16 + k];
+      tile_tgt[(size_t)tt * 16 + k] = leaf;
+      uni |= sig[leaf];
+    }
+    for (int c = 0; c < NCFG_U; ++c) {
+      if (!(uni >> c & 1)) continue;
+      slot_cfg.push_back(c);
+      for (int k = 0; k < 16; ++k) {
+        int leaf = tile_tgt[(size_t)tt * 16 + k], src = -1;
+        if (leaf >= 0)
+          for (int e = up[leaf]; e < up[leaf + 1]; ++e)
+            if (uc[e] == c) src = us[e];
+        slot_src.push_back(src);
+      }
+    }
+    tile_ptr[tt + 1] = (int)slot_cfg.size();
+  }
+  g.n_tiles = ntiles;
+  t->n_slots = (int64_t)slot_cfg.size();
+  if (ctx->flags & BX_HOST_ONLY) {
+    t->upload_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = t;
+    return BX_OK;
+  }
+  if ((rc = upload(t->dev, H.lvl, &g.lvl, s)) || (rc = upload(t->dev, H.child0, &g.child0, s)) ||
+      (rc = upload(t->dev, H.parent, &g.parent, s)) || (rc = upload(t->dev, H.leaf_of_box, &g.leaf_of_box, s)) ||
+      (rc = upload(t->dev, H.box_of_leaf, &g.box_of_leaf, s)) || (rc = upload(t->dev, leaf_level, &g.leaf_level, s)) ||
+      (rc = upload(t->dev, up, &g.u_ptr, s)) || (rc = upload(t->dev, us, &g.u_src, s)) ||
+      (rc = upload(t->dev, uc, &g.u_cfg, s)) || (rc = upload(t->dev, vp, &g.v_ptr, s)) ||
+      (rc = upload(t->dev, vs, &g.v_src, s)) || (rc = upload(t->dev, vc, &g.v_cfg, s)) ||
+      (rc = upload(t->dev, wp, &g.w_ptr, s)) || (rc = upload(t->dev, ws, &g.w_src, s)) ||
+      (rc = upload(t->dev, wc, &g.w_cfg, s)) || (rc = upload(t->dev, xp, &g.x_ptr, s)) ||
+      (rc = upload(t->dev, xs, &g.x_src, s)) || (rc = upload(t->dev, xc, &g.x_cfg, s)) ||
+      (rc = upload(t->dev, tile_tgt, &g.tile_tgt, s)) || (rc = upload(t->dev, tile_ptr, &g.tile_ptr, s)) ||
+      (rc = upload(t->dev, slot_cfg, &g.slot_cfg, s)) || (rc = upload(t->dev, slot_src, &g.slot_src, s))) {
+    bx_tree_destroy(t);
+    return rc;
+  }
+  // host vectors die at return: the copies must have completed
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    bx_tree_destroy(t);
+    return hip_fail(e, "bx_tree_upload");
+  }
+  t->upload_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = t;
+  return BX_OK;
+}
+
+static int ensure_expansions(bx_tree *t, int nrhs) {
+  if (t->exp_rhs >= nrhs) return BX_OK;
+  if (t->M) (void)hipFree(t->M);
+  if (t->L) (void)hipFree(t->L);
+  t->M = t->L = nullptr;
+  t->exp_rhs = 0;
+  size_t bytes = (size_t)nrhs * t->H.n_boxes * t->ctx->T.KP * 2 * sizeof(double);
+  hipError_t e = hipMalloc((void **)&t->M, bytes);
+  if (e == hipSuccess) e = hipMalloc((void **)&t->L, bytes);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(BX_E_OOM, "expansion buffers") : hip_fail(e, "hipMalloc");
+  t->exp_rhs = nrhs;
+  return BX_OK;
+}
+
+static int eval_impl(bx_ctx *ctx, const bx_tree *tree_c, const double *f, int nrhs, double *V, double *G,
+                     bx_stream_t stream) {
+  if (!ctx || !tree_c || !f || nrhs <= 0) return fail(BX_E_ARG, "volume eval: NULL argument or n_rhs <= 0");
+  if (!ctx->ready) return fail(BX_E_NO_TABLES, "volume eval: bx_build_tables has not been called");
+  if (ctx->flags & BX_HOST_ONLY) return fail(BX_E_UNSUPPORTED, "volume eval: host-only context");
+  bx_tree *t = const_cast<bx_tree *>(tree_c);
+  if (t->ctx != ctx) return fail(BX_E_ARG, "volume eval: tree belongs to another context");
+  if (((uintptr_t)f | (uintptr_t)V | (uintptr_t)G) & 7) return fail(BX_E_ARG, "volume eval: misaligned pointer");
+  int rc = ensure_expansions(t, nrhs);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const DevTables &d = ctx->dt;
+  const DevTree &g = t->dg;
+  const HostTree &H = t->H;
+  launch_p2m(d, g, f, nrhs, t->M, s);
+  for (int l = H.n_levels - 2; l >= 0; --l)
+    launch_m2m(d, g, l, H.level_start[l], H.level_start[l + 1], nrhs, t->M, s);
+  launch_m2l(d, g, nrhs, t->M, t->L, s);
+  launch_p2l(d, g, f, nrhs, t->L, s);
+  for (int l = 1; l < H.n_levels; ++l) launch_l2l(d, g, H.level_start[l], H.level_start[l + 1], nrhs, t->L, s);
+  launch_leaf_far(d, g, nrhs, t->M, t->L, V, G, s);
+  launch_near(d, g, f, nrhs, V, G, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return BX_OK;
+}
+
+int bx_volume_eval_grad(bx_ctx *ctx, const bx_tree *tree, const double *f_dev, int n_rhs, double *V_dev,
+                        double *G_dev, bx_stream_t stream) {
+  if (!V_dev || !G_dev) return fail(BX_E_ARG, "bx_volume_eval_grad: NULL output");
+  return eval_impl(ctx, tree, f_dev, n_rhs, V_dev, G_dev, stream);
+}
+
+static int scratch_eval(bx_ctx *ctx, const bx_tree *tree, const double *f, int nrhs, double *V, double *G,
+                        bool wantV, bx_stream_t stream) {
+  if (!ctx || !tree) return fail(BX_E_ARG, "volume eval: NULL argument");
+  size_t np = (size_t)nrhs * tree->H.n_leaves * ctx->T.P;
+  double *tmp = nullptr;
+  hipError_t e = hipMallocAsync((void **)&tmp, np * (wantV ? 2 : 1) * sizeof(double), (hipStream_t)stream);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(BX_E_OOM, "scratch output") : hip_fail(e, "hipMallocAsync");
+  int rc = wantV ? eval_impl(ctx, tree, f, nrhs, V, tmp, stream) : eval_impl(ctx, tree, f, nrhs, tmp, G, stream);
+  (void)hipFreeAsync(tmp, (hipStream_t)stream);
+  return rc;
+}
+
+int bx_volume_eval(bx_ctx *ctx, const bx_tree *tree, const double *f_dev, int n_rhs, double *V_dev,
+                   bx_stream_t stream) {
+  if (!V_dev) return fail(BX_E_ARG, "bx_volume_eval: NULL output");
+  return scratch_eval(ctx, tree, f_dev, n_rhs, V_dev, nullptr, true, stream);
+}
+
+int bx_volume_grad(bx_ctx *ctx, const bx_tree *tree, const double *f_dev, int n_rhs, double *G_dev,
+                   bx_stream_t stream) {
+  if (!G_dev) return fail(BX_E_ARG, "bx_volume_grad: NULL output");
+  return scratch_eval(ctx, tree, f_dev, n_rhs, nullptr, G_dev, false, stream);
+}
+
+int bx_query(const bx_ctx *ctx, const bx_tree *tree, int what, double *out) {
+  if (!ctx || !out) return fail(BX_E_ARG, "bx_query: NULL argument");
+  const Tables &T = ctx->T;
+  const int P = ctx->n * ctx->n, nt = ctx->p + 1;
+  switch (what) {
+    case BX_Q_NODES: *out = ctx->n; return BX_OK;
+    case BX_Q_ORDER: *out = ctx->p; return BX_OK;
+    default: break;
+  }
+  if (!tree) return fail(BX_E_ARG, "bx_query: this quantity needs a tree");
+  const HostTree &H = tree->H;
+  (void)T;
+  double nb_internal = 0;
+  for (int b = 0; b < H.n_boxes; ++b) nb_internal += H.leaf_of_box[b] < 0;
+  switch (what) {
+    case BX_Q_N_LEAVES: *out = H.n_leaves; break;
+    case BX_Q_N_BOXES: *out = H.n_boxes; break;
+    case BX_Q_N_LEVELS: *out = H.n_levels; break;
+    case BX_Q_NEAR_PAIRS: *out = (double)H.u_t.size(); break;
+    case BX_Q_V_PAIRS: *out = (double)H.v_t.size(); break;
+    case BX_Q_W_PAIRS: *out = (double)H.w_t.size(); break;
+    case BX_Q_X_PAIRS: *out = (double)H.x_t.size(); break;
+    case BX_Q_NEAR_FLOPS:   // 3P x P table product plus the P-term mass row, per U pair
+      *out = (double)H.u_t.size() * 2.0 * (3.0 * P + 1.0) * P;
+      break;
+    case BX_Q_FAR_FLOPS: {
+      double p2m = 2.0 * 2 * nt * P * H.n_leaves;              // real 2nt x P product
+      double m2m = 8.0 * nt * (nt + 1) / 2 * 4 * nb_internal;   // 4 triangular complex products
+      double l2l = 8.0 * nt * (nt + 1) / 2 * (H.n_boxes - 1);
+      double m2l = (double)H.v_t.size() * (4.0 * nt * nt + 12.0 * nt);   // real core on complex data + scalings
+      double x = (double)H.x_t.size() * 2.0 * 2 * nt * P;
+      double w = (double)H.w_t.size() * 2.0 * 3 * P * 2 * nt;
+      double l2t = 2.0 * 3 * P * 2 * nt * H.n_leaves;
+      *out = p2m + m2m + l2l + m2l + x + w + l2t;
+      break;
+    }
+    case BX_Q_NEAR_TILES: *out = tree->dg.n_tiles; break;
+    case BX_Q_NEAR_SLOTS: *out = (double)tree->n_slots; break;
+    case BX_Q_UPLOAD_MS: *out = tree->upload_ms; break;
+    default: return fail(BX_E_ARG, "bx_query: unknown quantity");
+  }
+  return BX_OK;
+}
+
+int bx_table_copy(const bx_ctx *ctx, int which, double *out, int64_t cap, int64_t *count) {
+  if (!ctx || !count) return fail(BX_E_ARG, "bx_table_copy: NULL argument");
+  if (!ctx->ready) return fail(BX_E_NO_TABLES, "bx_table_copy: bx_build_tables has not been called");
+  const Tables &T = ctx->T;
+  const std::vector<double> *v[12] = {&T.near_, &T.p2m, &T.m2m, &T.l2l, &T.H, &T.pw_src,
+                                      &T.pw_tgt, &T.logd, &T.l2t, &T.m2t, &T.p2l, &T.wq};
+  if (which < 0 || which >= 12) return fail(BX_E_ARG, "bx_table_copy: unknown table");
+  *count = (int64_t)v[which]->size();
+  if (out) std::memcpy(out, v[which]->data(), (size_t)std::min<int64_t>(cap, *count) * sizeof(double));
+  return BX_OK;
+}
+
+int bx_tree_list(const bx_tree *tree, int kind, int64_t *out, int64_t cap, int64_t *count) {
+  if (!tree || !count) return fail(BX_E_ARG, "bx_tree_list: NULL argument");
+  const HostTree &H = tree->H;
+  const std::vector<int> *T = nullptr, *S = nullptr, *C = nullptr;
+  bool tbox = false, sbox = false;
+  switch (kind) {
+    case 0: T = &H.u_t; S = &H.u_s; C = &H.u_c; break;
+    case 1: T = &H.v_t; S = &H.v_s; C = &H.v_c; tbox = sbox = true; break;
+    case 2: T = &H.w_t; S = &H.w_s; C = &H.w_c; sbox = true; break;
+    case 3: T = &H.x_t; S = &H.x_s; C = &H.x_c; tbox = true; break;
+    default: return fail(BX_E_ARG, "bx_tree_list: unknown kind");
+  }
+  *count = (int64_t)T->size();
+  if (!out) return BX_OK;
+  auto key = [&](int b) { return (int64_t)box_key(H.lvl[b], H.bx[b], H.by[b]); };
+  int64_t m = std::min<int64_t>(cap, *count);
+  for (int64_t i = 0; i < m; ++i) {
+    out[3 * i] = tbox ? key((*T)[i]) : (*T)[i];
+    out[3 * i + 1] = sbox ? key((*S)[i]) : (*S)[i];
+    out[3 * i + 2] = (*C)[i];
+  }
+  return BX_OK;
+}
+
+void bx_tree_destroy(bx_tree *tree) {
+  if (!tree) return;
+  for (void *p : tree->dev) (void)hipFree(p);
+  if (tree->M) (void)hipFree(tree->M);
+  if (tree->L) (void)hipFree(tree->L);
+  delete tree;
+}
+
+void bx_destroy(bx_ctx *ctx) {
+  if (!ctx) return;
+  for (void *p : ctx->dev) (void)hipFree(p);
+  delete ctx;
+}
+
+}  // extern "C"

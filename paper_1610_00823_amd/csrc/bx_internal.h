@@ -1,0 +1,75 @@
+// Internal declarations of the box-code library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/boxfmm.h"
+
+namespace bx {
+
+constexpr int NCFG_U = 33;   // near (U-list) configurations of a level-restricted tree
+constexpr int NCFG_W = 20;   // fine non-adjacent boxes whose parents are adjacent (W list)
+constexpr int NCFG_X = 20;   // coarse non-adjacent leaves adjacent to the parent (X list)
+constexpr int NOFF = 49;     // 7 x 7 same-level offsets; the 40 with max(|dx|,|dy|) >= 2 are V-list classes
+
+// Geometry of a source box relative to a unit target box centred at 0.
+struct Rel {
+  double cx, cy, w;
+};
+void u_configs(Rel out[NCFG_U]);
+// W and X positions: lower-left (a, b) of the smaller box relative to the
+// lower-left of the larger one, in units of the smaller box's width.
+void wx_positions(int a[NCFG_W], int b[NCFG_W]);
+
+// Unit-box operators in FP64 (host).  KP = expansion length padded to 16.
+struct Tables {
+  int n = 0, P = 0, p = 0, nt = 0, KP = 0;
+  int MR = 0;                      // near rows: 3P + 1 (mass row) padded to 16
+  std::vector<double> wq;          // [P] weights int L_j over the unit box
+  std::vector<double> near_;       // [33][MR][P]: rows V (P), d1 (P), d2 (P), mass (1)
+  std::vector<double> p2m;         // [2 KP][P]: Re a_k rows then Im a_k rows
+  std::vector<double> m2m;         // [4][nt][nt][2] complex, child position c = cx + 2 cy
+  std::vector<double> l2l;         // [4][nt][nt][2] complex
+  std::vector<double> H;           // [KP][KP] real, M2L core (row l, column k)
+  std::vector<double> pw_src;      // [49][KP][2] (-d/2)^-k
+  std::vector<double> pw_tgt;      // [49][KP][2] (d/2)^-l
+  std::vector<double> logd;        // [49] log|d|
+  std::vector<double> l2t;         // [3P][2 KP]: columns Re b_l then Im b_l
+  std::vector<double> m2t;         // [20][3P][2 KP]
+  std::vector<double> p2l;         // [20][2 KP][P]
+};
+
+int build_tables(Tables &T, int n, int p, double tol, int nthreads);
+uint64_t tables_checksum(const Tables &T);
+bool save_tables(const Tables &T, const std::string &path);
+bool load_tables(Tables &T, const std::string &path, int n, int p);
+
+// Host tree: box hierarchy and interaction lists.
+inline uint64_t box_key(int l, int64_t x, int64_t y) {
+  return ((uint64_t)l << 58) | ((uint64_t)x << 29) | (uint64_t)y;
+}
+
+struct HostTree {
+  double cx = 0, cy = 0, width = 1;
+  int n_leaves = 0, n_boxes = 0, n_levels = 0;
+  std::vector<int> lvl, bx, by;           // per box (sorted by level, then Morton)
+  std::vector<int> parent, child0;        // child0 = first of 4 contiguous children, -1 for a leaf
+  std::vector<int> leaf_of_box;           // descriptor index, -1 for internal boxes
+  std::vector<int> box_of_leaf;           // [n_leaves]
+  std::vector<int> level_start;           // [n_levels + 1]
+  // lists: (target, source, config)
+  std::vector<int> u_t, u_s, u_c;         // target leaf, source leaf (descriptor indices)
+  std::vector<int> v_t, v_s, v_c;         // target box, source box, offset class (0..48)
+  std::vector<int> w_t, w_s, w_c;         // target leaf, source box, config
+  std::vector<int> x_t, x_s, x_c;         // target box, source leaf, config
+};
+
+int build_tree(HostTree &T, const bx_tree_desc &d, std::string &err);
+
+void set_error(const std::string &msg);
+
+}  // namespace bx

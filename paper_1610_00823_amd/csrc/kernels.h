@@ -1,0 +1,52 @@
+// Device kernels of the box code and their host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bx {
+
+// Device copies of the unit-box operators (see bx_internal.h for layouts).
+struct DevTables {
+  int n, P, p, nt, KP, MR;
+  const double *wq, *near_, *near_frag, *p2m, *m2m, *l2l, *H, *pw_src, *pw_tgt, *logd, *l2t, *m2t, *p2l;
+};
+
+// Device copy of a tree's hierarchy and lists (CSR by target, sorted).
+struct DevTree {
+  int n_leaves, n_boxes, n_levels;
+  double width;
+  const int *lvl;          // [NB]
+  const int *child0;       // [NB]
+  const int *parent;       // [NB]
+  const int *leaf_of_box;  // [NB]
+  const int *box_of_leaf;  // [NL]
+  const int *leaf_level;   // [NL]
+  // U: per target leaf, CSR of (source leaf, config)
+  const int *u_ptr, *u_src, *u_cfg;
+  // V: per target box, CSR of (source box, offset class)
+  const int *v_ptr, *v_src, *v_cfg;
+  // W: per target leaf, CSR of (source box, config)
+  const int *w_ptr, *w_src, *w_cfg;
+  // X: per target box, CSR of (source leaf, config)
+  const int *x_ptr, *x_src, *x_cfg;
+  // near kernel tiling: 16-target tiles, slots of (config, 16 sources)
+  int n_tiles;
+  const int *tile_tgt;     // [n_tiles][16], -1 = padding
+  const int *tile_ptr;     // [n_tiles + 1] into slots
+  const int *slot_cfg;     // [n_slots]
+  const int *slot_src;     // [n_slots][16], -1 = none
+};
+
+// Expansion storage: [n_rhs][NB][KP] complex (interleaved re, im).
+void launch_p2m(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *M, hipStream_t s);
+void launch_m2m(const DevTables &t, const DevTree &g, int level, int box0, int box1, int nrhs, double *M,
+                hipStream_t s);
+void launch_m2l(const DevTables &t, const DevTree &g, int nrhs, const double *M, double *L, hipStream_t s);
+void launch_p2l(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *L, hipStream_t s);
+void launch_l2l(const DevTables &t, const DevTree &g, int box0, int box1, int nrhs, double *L, hipStream_t s);
+void launch_leaf_far(const DevTables &t, const DevTree &g, int nrhs, const double *M, const double *L, double *V,
+                     double *G, hipStream_t s);
+void launch_near(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *V, double *G,
+                 hipStream_t s);
+
+}  // namespace bx

@@ -1,0 +1,136 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, on the GPU.
+
+Error metric E(psi) = max|psi - psi_oracle| / max|psi_oracle| over the
+evaluated nodes (section 6's relative L-infinity error); the FP64 path must
+reach 1e-12 for V and for each gradient component.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1610_00823_amd import boxfmm as B
+from paper_1610_00823_amd import inputs as I
+from tests import closed_forms as CF
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx8():
+    _torch()
+    return B.Context(8, 30, B.BX_FP64)
+
+
+def gpu_eval(ctx, tree, f, nrhs=None):
+    torch = _torch()
+    tr = B.Tree.from_inputs(ctx, tree)
+    fd = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    V, G = B.volume_eval_grad(ctx, tr, fd)
+    torch.cuda.synchronize()
+    return V.cpu().numpy(), G.cpu().numpy(), tr
+
+
+def E(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def check_vs_oracle(tree, f, V, G, leaves=None, tol=TOL):
+    n = f.shape[-1]
+    Vo, Gxo, Gyo = oracle.volume_at_nodes(tree.level, tree.ix, tree.iy, f, leaves=leaves, cx=tree.cx,
+                                          cy=tree.cy, width=tree.width)
+    sel = slice(None) if leaves is None else leaves
+    ev, ex, ey = E(V[sel], Vo), E(G[sel, 0], Gxo), E(G[sel, 1], Gyo)
+    print(f"E(V)={ev:.2e} E(dV/dx1)={ex:.2e} E(dV/dx2)={ey:.2e}")
+    assert ev < tol and ex < tol and ey < tol
+    return ev, ex, ey
+
+
+def test_constant_source_closed_form(ctx8):
+    # f = 1 is exact on any tree: the whole pipeline against the rectangle formula.
+    for t in (I.uniform_tree(3), I.point_refined_tree([[0.3, 0.2], [-0.26, -0.4]], [5, 4])):
+        f = np.ones((t.n_leaves, 8, 8))
+        V, G, _ = gpu_eval(ctx8, t, f)
+        X, Y = oracle.leaf_nodes(t.level, t.ix, t.iy, 8)
+        Ve, gxe, gye = CF.const_rect(X, Y, -0.5, 0.5, -0.5, 0.5)
+        assert E(V[0], Ve) < TOL and E(G[0, :, 0], gxe) < TOL and E(G[0, :, 1], gye) < TOL
+
+
+def test_single_leaf_and_two_levels(ctx8):
+    rng = np.random.default_rng(11)
+    for depth in (0, 1, 2):
+        t = I.uniform_tree(depth)
+        f = rng.standard_normal((t.n_leaves, 8, 8))
+        V, G, _ = gpu_eval(ctx8, t, f)
+        check_vs_oracle(t, f, V[0], G[0])
+
+
+def test_uniform_depth4_gaussian_all_nodes(ctx8):
+    # 256 leaves, 8x8 nodes, p = 30, f = exp(-|x|^2 / 0.1^2): every node.
+    t, src = I.workload("uniform4_gauss")
+    f = I.sample(t, src, 8)
+    V, G, _ = gpu_eval(ctx8, t, f)
+    check_vs_oracle(t, f, V[0], G[0])
+    # and against the closed form within the discretisation bound
+    X, Y = oracle.leaf_nodes(t.level, t.ix, t.iy, 8)
+    Ve, gxe, gye = CF.radial_gaussian(X, Y, 0.1)
+    assert np.abs(V[0] - Ve).max() < 1e-8
+
+
+def test_graded_tree_random_source_all_nodes(ctx8):
+    # Every near (same, coarse, fine), W, X and V configuration occurs here.
+    t = I.point_refined_tree([[0.3, 0.2], [-0.26, -0.4], [0.45, -0.45], [-0.1, 0.33]], [5, 4, 6, 3])
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal((t.n_leaves, 8, 8))
+    V, G, tr = gpu_eval(ctx8, t, f)
+    assert tr.query("w_pairs") > 0 and tr.query("x_pairs") > 0
+    check_vs_oracle(t, f, V[0], G[0])
+
+
+def test_multi_rhs_equals_single(ctx8):
+    torch = _torch()
+    t = I.point_refined_tree([[0.2, -0.3]], [4])
+    rng = np.random.default_rng(9)
+    f = rng.standard_normal((3, t.n_leaves, 8, 8))
+    tr = B.Tree.from_inputs(ctx8, t)
+    V3, G3 = B.volume_eval_grad(ctx8, tr, torch.from_numpy(f).cuda())
+    for r in range(3):
+        V1, G1 = B.volume_eval_grad(ctx8, tr, torch.from_numpy(f[r].copy()).cuda())
+        assert torch.equal(V1[0], V3[r]) and torch.equal(G1[0], G3[r])
+
+
+def test_eval_and_grad_entry_points_agree(ctx8):
+    torch = _torch()
+    t = I.uniform_tree(3)
+    f = torch.from_numpy(np.random.default_rng(3).standard_normal((t.n_leaves, 8, 8))).cuda()
+    tr = B.Tree.from_inputs(ctx8, t)
+    V, G = B.volume_eval_grad(ctx8, tr, f)
+    assert torch.equal(B.volume_eval(ctx8, tr, f), V)
+    assert torch.equal(B.volume_grad(ctx8, tr, f), G)
+
+
+def test_adaptive_gaussians_sampled_targets(ctx8):
+    # 20 Gaussians, tail tolerance 1e-10, depth <= 14: about 42k leaves.  The
+    # oracle checks a seeded sample of leaves stratified by level.
+    t, src = I.workload("gauss20_s0")
+    f = I.sample(t, src, 8)
+    V, G, _ = gpu_eval(ctx8, t, f)
+    rng = np.random.default_rng(0)
+    sel = []
+    for l in np.unique(t.level):
+        idx = np.flatnonzero(t.level == l)
+        sel += list(rng.choice(idx, min(len(idx), 6), replace=False))
+    sel = np.array(sorted(sel))
+    Vo, Gxo, Gyo = oracle.volume_at_nodes(t.level, t.ix, t.iy, f, leaves=sel)
+    # normalise by the maxima over all nodes (the oracle's sample maxima are a lower bound)
+    ev = np.abs(V[0][sel] - Vo).max() / np.abs(V[0]).max()
+    ex = np.abs(G[0][sel, 0] - Gxo).max() / np.abs(G[0][:, 0]).max()
+    ey = np.abs(G[0][sel, 1] - Gyo).max() / np.abs(G[0][:, 1]).max()
+    print(f"sampled {len(sel)} leaves: E(V)={ev:.2e} E(dV/dx1)={ex:.2e} E(dV/dx2)={ey:.2e}")
+    assert ev < TOL and ex < TOL and ey < TOL

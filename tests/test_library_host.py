@@ -1,0 +1,303 @@
+"""Host-side checks of the C-ABI library (no GPU): exported symbols, tree
+validation, interaction-list coverage, and the FP64 unit-box operators
+against the oracle and against direct point-charge sums."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1610_00823_amd import boxfmm as B
+from paper_1610_00823_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "boxfmm.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(bx_\w+)\s*\(", hdr, re.M))
+    assert {"bx_create", "bx_build_tables", "bx_tree_upload", "bx_volume_eval", "bx_volume_grad",
+            "bx_volume_eval_grad", "bx_query", "bx_tree_destroy", "bx_destroy", "bx_last_error"} <= declared
+    lib = ctypes.CDLL(B.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(B.SYMBOLS)
+
+
+@pytest.fixture(scope="module")
+def host8():
+    return B.Context(8, 30, B.BX_FP64 | B.BX_HOST_ONLY)
+
+
+def _tree(ctx, t):
+    return B.Tree.from_inputs(ctx, t)
+
+
+def test_bad_arguments_give_error_codes():
+    with pytest.raises(B.BoxFMMError) as e:
+        B.Context(5, 30, B.BX_HOST_ONLY, build=False)
+    assert e.value.code == B.BX_E_UNSUPPORTED
+    with pytest.raises(B.BoxFMMError) as e:
+        B.Context(8, 60, B.BX_HOST_ONLY, build=False)
+    assert e.value.code == B.BX_E_UNSUPPORTED
+    ctx = B.Context(4, 16, B.BX_HOST_ONLY, build=False)
+    t = I.uniform_tree(1)
+    # a host-only context evaluates nothing
+    tr = _tree(ctx, t)
+    assert tr.query("n_boxes") == 5
+
+
+def test_tree_validation_errors(host8):
+    # hole
+    with pytest.raises(B.BoxFMMError) as e:
+        B.Tree(host8, [1, 1, 1], [0, 1, 0], [0, 0, 1])
+    assert e.value.code == B.BX_E_INVALID_TREE
+    # overlap
+    with pytest.raises(B.BoxFMMError) as e:
+        B.Tree(host8, [0, 1, 1, 1, 1], [0, 0, 1, 0, 1], [0, 0, 0, 1, 1])
+    assert e.value.code == B.BX_E_INVALID_TREE
+    # repeated leaf with a hole elsewhere keeps the area right
+    with pytest.raises(B.BoxFMMError) as e:
+        B.Tree(host8, [1, 1, 1, 1], [0, 0, 1, 0], [0, 0, 0, 1])
+    assert e.value.code == B.BX_E_INVALID_TREE
+    # outside the root
+    with pytest.raises(B.BoxFMMError) as e:
+        B.Tree(host8, [1, 1, 1, 1], [0, 1, 0, 2], [0, 0, 1, 1])
+    assert e.value.code == B.BX_E_INVALID_TREE
+    # not level-restricted: a level-3 leaf next to a level-1 leaf
+    lv, xs, ys = [], [], []
+    for q in range(4):
+        if q == 0:
+            for r in range(4):
+                if r == 3:
+                    for s_ in range(4):
+                        lv.append(3); xs.append(2 + (s_ & 1)); ys.append(2 + (s_ >> 1))
+                else:
+                    lv.append(2); xs.append(r & 1); ys.append(r >> 1)
+        else:
+            lv.append(1); xs.append(q & 1); ys.append(q >> 1)
+    with pytest.raises(B.BoxFMMError) as e:
+        B.Tree(host8, lv, xs, ys)
+    assert e.value.code == B.BX_E_NOT_BALANCED
+    assert "level-restricted" in B.lib().bx_last_error().decode()
+
+
+def _decode(key):
+    return int(key) >> 58, (int(key) >> 29) & ((1 << 29) - 1), int(key) & ((1 << 29) - 1)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "graded", "gauss"])
+def test_every_source_target_pair_is_counted_once(host8, kind):
+    # Brute force over all (source leaf, target leaf) pairs: U + W + V + X along
+    # the target's ancestors must cover each pair exactly once, and U must be
+    # exactly the touching leaves (the near field of section 3.1).
+    if kind == "uniform":
+        t = I.uniform_tree(3)
+    elif kind == "graded":
+        t = I.point_refined_tree([[0.3, 0.2], [-0.26, -0.4], [0.45, -0.45]], [5, 4, 6])
+    else:
+        src = I.random_gaussians(3, 6, log_sigma=(1e-2, 1e-1))
+        t = I.gaussian_tree(src, 4, 1e-6, 7)
+    tr = _tree(host8, t)
+    lv, xs, ys = t.level.astype(np.int64), t.ix.astype(np.int64), t.iy.astype(np.int64)
+    NL = len(lv)
+
+    def inside(box):      # mask of leaves contained in box (l, x, y)
+        l, x, y = box
+        sh = np.maximum(lv - l, 0)
+        return (lv >= l) & ((xs >> sh) == x) & ((ys >> sh) == y)
+
+    def touching(box):    # mask of leaves whose closed squares touch box
+        l, x, y = box
+        L = np.maximum(lv, l)
+        s1, s2 = np.left_shift(1, L - l), np.left_shift(1, L - lv)
+        return ((x * s1 <= (xs + 1) * s2) & (xs * s2 <= (x + 1) * s1) &
+                (y * s1 <= (ys + 1) * s2) & (ys * s2 <= (y + 1) * s1))
+
+    cnt = np.zeros((NL, NL), np.int64)      # [target, source]
+    U = tr.lists(0)
+    assert ((U[:, 2] >= 0) & (U[:, 2] < 33)).all()
+    np.add.at(cnt, (U[:, 0], U[:, 1]), 1)
+    for tl, skey, c in tr.lists(2):
+        sb = _decode(skey)
+        assert sb[0] == lv[tl] + 1 and not touching(sb)[tl]
+        cnt[tl] += inside(sb)
+    # V and X entries of every ancestor-or-self box of each target leaf
+    for tk, sk, c in tr.lists(1):
+        tb, sb = _decode(tk), _decode(sk)
+        assert tb[0] == sb[0] and max(abs(tb[1] - sb[1]), abs(tb[2] - sb[2])) >= 2
+        cnt[np.ix_(inside(tb), inside(sb))] += 1
+    for tk, sl, c in tr.lists(3):
+        tb = _decode(tk)
+        assert lv[sl] == tb[0] - 1 and not touching(tb)[sl]
+        cnt[inside(tb), sl] += 1
+    assert (cnt == 1).all(), np.argwhere(cnt != 1)[:5]
+    touch = np.array([touching((lv[i], xs[i], ys[i])) for i in range(NL)])
+    ucnt = np.zeros((NL, NL), bool)
+    ucnt[U[:, 0], U[:, 1]] = True
+    assert (ucnt == touch).all()
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_near_tables_match_oracle(n):
+    # Table column j for configuration c is the potential (and gradient) of the
+    # j-th Lagrange basis function on that source box, at the unit target box's
+    # nodes: the oracle computes exactly that with its own quadrature.
+    ctx = B.Context(n, 16, B.BX_FP64 | B.BX_HOST_ONLY)
+    P = n * n
+    MR = (3 * P + 1 + 15) // 16 * 16
+    near = ctx.table("near").reshape(33, MR, P)
+    assert np.isfinite(near).all()
+    xi = oracle.cheb_nodes(n)
+    TX, TY = np.meshgrid(0.5 * xi, 0.5 * xi)
+    cfgs = [(dx, dy, 1.0) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    for q in range(4):
+        cx, cy = q & 1, q >> 1
+        ex, ey = (1 if cx else -1), (1 if cy else -1)
+        cfgs += [(2 * e[0] - (cx - 0.5), 2 * e[1] - (cy - 0.5), 2.0) for e in ((ex, 0), (0, ey), (ex, ey))]
+    cfgs += [((a + 0.5) / 2 - 0.5, (b + 0.5) / 2 - 0.5, 0.5) for b in range(-1, 3) for a in range(-1, 3)
+             if not (0 <= a <= 1 and 0 <= b <= 1)]
+    rng = np.random.default_rng(0)
+    wq = ctx.table("weights")
+    for c, (sx, sy, sw) in enumerate(cfgs):
+        for j in rng.choice(P, 3, replace=False):
+            f = np.zeros((1, n, n))
+            f.ravel()[j] = 1.0
+            V, gx, gy = oracle.volume([0], [0], [0], f, TX.ravel(), TY.ravel(), cx=sx, cy=sy, width=sw)
+            assert np.abs(near[c, :P, j] - V).max() < 2e-14
+            assert np.abs(near[c, P:2 * P, j] - gx).max() < 2e-14
+            assert np.abs(near[c, 2 * P:3 * P, j] - gy).max() < 2e-14
+            # mass row: sw^2 times the unit-box weight
+            assert abs(near[c, 3 * P, j] - sw * sw * wq[j]) < 1e-16
+    assert abs(wq.sum() - 1.0) < 1e-14
+
+
+def _cheb_basis(n, t):
+    xi = oracle.cheb_nodes(n)
+    L = np.ones((len(t), n))
+    for j in range(n):
+        for k in range(n):
+            if k != j:
+                L[:, j] *= (t - xi[k]) / (xi[j] - xi[k])
+    return L
+
+
+def test_expansion_operators_against_point_charges():
+    # Charges in a unit box, their potential far away, and the same through
+    # P2M/M2M/M2L/L2L/L2T built from the library's tables (complex log expansions).
+    p = 30
+    ctx = B.Context(4, p, B.BX_FP64 | B.BX_HOST_ONLY)
+    nt = p + 1
+    KP = (nt + 15) // 16 * 16
+    m2m = ctx.table("m2m").reshape(4, nt, nt, 2)
+    m2m = m2m[..., 0] + 1j * m2m[..., 1]
+    l2l = ctx.table("l2l").reshape(4, nt, nt, 2)
+    l2l = l2l[..., 0] + 1j * l2l[..., 1]
+    H = ctx.table("m2l_core").reshape(KP, KP)[:nt, :nt]
+    ps = ctx.table("m2l_src_pow").reshape(49, KP, 2)
+    pt = ctx.table("m2l_tgt_pow").reshape(49, KP, 2)
+    logd = ctx.table("logd")
+    rng = np.random.default_rng(1)
+    h = 0.25
+    # child box (position q=3 -> upper right) of parent centred at 0 with width 2h
+    q = 3
+    cc = complex(((q & 1) - 0.5) * h, ((q >> 1) - 0.5) * h)
+    zs = cc + (rng.uniform(-0.5, 0.5, 20) + 1j * rng.uniform(-0.5, 0.5, 20)) * h
+    qs = rng.standard_normal(20)
+    a = np.array([qs.sum()] + [-(qs * ((zs - cc) / h) ** k).sum() / k for k in range(1, nt)])   # scaled multipole
+    ap = m2m[q] @ a                      # parent multipole, scaled by 2h
+    z = 3.1 + 2.2j
+    direct = (qs * np.log(np.abs(z - zs))).sum()
+    viaP = ap[0] * np.log(abs(z)) + (ap[1:] * (2 * h / z) ** np.arange(1, nt)).sum()
+    assert abs(viaP.real - direct) < 1e-13
+    # M2L at the parent's level: target box at offset (3, 2) parent widths
+    dx, dy = 3, 2
+    o = (dy + 3) * 7 + (dx + 3)
+    H2 = 2 * h
+    y = ap * (ps[o, :nt, 0] + 1j * ps[o, :nt, 1])
+    b = (pt[o, :nt, 0] + 1j * pt[o, :nt, 1]) * (H @ y)
+    b[0] += ap[0] * (np.log(H2) + logd[o])
+    ct = -complex(dx, dy) * H2          # source at the parent centre 0 = ct + d*H2
+    for zt in (ct + 0.3 * H2 + 0.1j * H2, ct - 0.45 * H2 - 0.45j * H2):
+        u = (zt - ct) / H2
+        viaL = (b * u ** np.arange(nt)).sum().real
+        direct = (qs * np.log(np.abs(zt - zs))).sum()
+        assert abs(viaL - direct) < 1e-12 * np.abs(qs).sum()
+        # L2L into child 1 of the target box, then evaluate
+        cq = 1
+        ccz = ct + complex(((cq & 1) - 0.5) * h, ((cq >> 1) - 0.5) * h)
+        bc = l2l[cq] @ b
+        u2 = (zt - ccz) / h
+        assert abs((bc * u2 ** np.arange(nt)).sum().real - viaL) < 1e-13
+
+
+def test_l2t_m2t_p2l_p2m_against_direct_sums():
+    n, p = 4, 30
+    ctx = B.Context(n, p, B.BX_FP64 | B.BX_HOST_ONLY)
+    P, nt = n * n, p + 1
+    KP = (nt + 15) // 16 * 16
+    xi = oracle.cheb_nodes(n)
+    # L2T: local expansion of far charges; V and gradient at the nodes
+    rng = np.random.default_rng(2)
+    zs = 5.0 + 3j + rng.standard_normal(6) + 1j * rng.standard_normal(6)
+    qs = rng.standard_normal(6)
+    h = 0.5
+    b = np.array([(qs * np.log(np.abs(zs))).sum()] + [-(qs * (zs / h) ** (-l)).sum() / l for l in range(1, nt)])
+    vec = np.concatenate([np.pad(b.real, (0, KP - nt)), np.pad(b.imag, (0, KP - nt))])
+    out = ctx.table("l2t").reshape(3 * P, 2 * KP) @ vec
+    X, Y = np.meshgrid(0.5 * h * xi, 0.5 * h * xi)
+    zt = (X + 1j * Y).ravel()
+    dV = (qs[None, :] * np.log(np.abs(zt[:, None] - zs[None, :]))).sum(1) / (2 * np.pi)
+    dz = zt[:, None] - zs[None, :]
+    g = (qs[None, :] * dz / np.abs(dz) ** 2).sum(1) / (2 * np.pi)
+    assert np.abs(out[:P] - dV).max() < 1e-13
+    assert np.abs(out[P:2 * P] / h - g.real).max() < 1e-12 and np.abs(out[2 * P:] / h - g.imag).max() < 1e-12
+    # P2M of the interpolant equals the moments of f~ (exact integrals by Gauss rules)
+    p2m = ctx.table("p2m").reshape(2 * KP, P)
+    f = rng.standard_normal(P)
+    gx, gw = np.polynomial.legendre.leggauss(24)
+    L = _cheb_basis(n, gx)
+    F = np.einsum("aj,bi,ij->ab", L, L, f.reshape(n, n))    # F[a, b] = f~(gx[a], gx[b]), x fastest in f
+    v = 0.5 * (gx[:, None] + 1j * gx[None, :])          # v[a, b] = (x_a + i y_b)/2
+    W = 0.25 * gw[:, None] * gw[None, :]
+    mom = np.array([(W * F).sum()] + [-(W * F * v ** k).sum() / k for k in range(1, nt)])
+    got = p2m[:nt] @ f + 1j * (p2m[KP:KP + nt] @ f)
+    assert np.abs(got - mom).max() < 1e-14
+    # M2T from a fine W box: its multipole evaluated at the nodes vs direct sums
+    m2t = ctx.table("m2t").reshape(20, 3 * P, 2 * KP)
+    a_pos = [(i, j) for j in range(-2, 4) for i in range(-2, 4) if not (-1 <= i <= 2 and -1 <= j <= 2)]
+    c = 7
+    ai, bi = a_pos[c]
+    H = 1.0
+    hs = H / 2
+    cs = complex(-0.5 * H + (ai + 0.5) * hs, -0.5 * H + (bi + 0.5) * hs)
+    zs = cs + hs * (rng.uniform(-0.5, 0.5, 8) + 1j * rng.uniform(-0.5, 0.5, 8))
+    qs = rng.standard_normal(8)
+    a = np.array([qs.sum()] + [-(qs * ((zs - cs) / hs) ** k).sum() / k for k in range(1, nt)])
+    vec = np.concatenate([np.pad(a.real, (0, KP - nt)), np.pad(a.imag, (0, KP - nt))])
+    out = m2t[c] @ vec
+    X, Y = np.meshgrid(0.5 * H * xi, 0.5 * H * xi)
+    zt = (X + 1j * Y).ravel()
+    V = out[:P] + a[0].real * np.log(hs) / (2 * np.pi)
+    dz = zt[:, None] - zs[None, :]
+    assert np.abs(V - (qs * np.log(np.abs(dz))).sum(1) / (2 * np.pi)).max() < 1e-12
+    g = (qs * dz / np.abs(dz) ** 2).sum(1) / (2 * np.pi)
+    assert np.abs(out[P:2 * P] / hs - g.real).max() < 1e-11 and np.abs(out[2 * P:] / hs - g.imag).max() < 1e-11
+    # P2L from a coarse X leaf: local expansion of f~ on the leaf vs the oracle
+    p2l = ctx.table("p2l").reshape(20, 2 * KP, P)
+    wq = ctx.table("weights")
+    c = 3
+    ai, bi = a_pos[c]
+    h = 0.25                                   # target width; coarse leaf width 2h at [0, 2h]^2
+    tcx, tcy = (ai + 0.5) * h, (bi + 0.5) * h
+    f = rng.standard_normal(P)
+    bl = h * h * (p2l[c, :nt] @ f) + 1j * h * h * (p2l[c, KP:KP + nt] @ f)
+    bl[0] += h * h * np.log(h) * 4 * (wq @ f)
+    pts = np.array([[0.3, -0.2], [-0.45, 0.41]])
+    tx, ty = tcx + h * pts[:, 0], tcy + h * pts[:, 1]
+    Vo, _, _ = oracle.volume([0], [0], [0], f.reshape(1, n, n), tx, ty, cx=h, cy=h, width=2 * h)
+    u = pts[:, 0] + 1j * pts[:, 1]
+    Vl = np.array([(bl * uu ** np.arange(nt)).sum().real for uu in u]) / (2 * np.pi)
+    assert np.abs(Vl - Vo).max() < 1e-12
