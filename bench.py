@@ -1,0 +1,153 @@
+"""Benchmark of the box-code volume potential V + grad V on one MI355X.
+
+One step = one bx_volume_eval_grad over the whole tree (P2M, M2M, M2L, X, L2L,
+leaf far field, near tables) with f, V, G, tables and lists resident on the
+GPU.  Prints one JSON line.  The default workload is the adaptive 20-Gaussian
+source (seed 0, tail tolerance 1e-10, depth <= 14, 8x8 nodes, p = 30).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "leaf-points/sec for V+\u2207V at 1e-10 rel err, mixed vs plain FP64 (1 MI355X)"
+PEAK_FP64 = 78.6e12          # MI355X dense FP64 (vector and matrix), FLOP/s
+PEAK_HBM = 8.0e12            # B/s
+# how each phase's kernel is bound, and by what
+BOUND = {"leaf": ("mfma", PEAK_FP64), "m2l": ("mfma", PEAK_FP64), "p2m": ("mfma", PEAK_FP64),
+         "p2l": ("alu", PEAK_FP64), "m2m": ("alu", PEAK_FP64), "l2l": ("alu", PEAK_FP64)}
+KERNEL_OF = {"leaf": "leaf_mfma_kernel", "m2l": "m2l_mfma_kernel", "p2m": "p2m_mfma_kernel",
+             "p2l": "p2l_kernel", "m2m": "m2m_kernel", "l2l": "l2l_kernel"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(tree, f, target_s=15.0, seed=0):
+    """The oracle on a seeded, level-stratified sample of leaves (all their nodes)."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    levels = np.unique(tree.level)
+    order = []
+    pools = {l: list(rng.permutation(np.flatnonzero(tree.level == l))) for l in levels}
+    while any(pools.values()):
+        for l in levels:
+            if pools[l]:
+                order.append(pools[l].pop())
+    n = f.shape[-1]
+    t0 = time.perf_counter()
+    oracle.volume_at_nodes(tree.level, tree.ix, tree.iy, f, leaves=np.array(order[:2]))
+    t_probe = max(time.perf_counter() - t0, 1e-3)
+    k = int(min(len(order), max(2, 2 * target_s / t_probe)))
+    sel = np.array(order[:k])
+    t0 = time.perf_counter()
+    oracle.volume_at_nodes(tree.level, tree.ix, tree.iy, f, leaves=sel)
+    dt = time.perf_counter() - t0
+    pts = k * n * n
+    return {"value": pts / dt, "unit": "leaf-points/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{k} leaves ({pts} nodes, seeded, stratified by level) of the same tree, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="gauss20_s0")
+    ap.add_argument("--n", type=int, default=8)
+    ap.add_argument("--p", type=int, default=30)
+    ap.add_argument("--precision", choices=["fp64", "split"], default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "the multi-GPU sharding is a design, not code.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1610_00823_amd import boxfmm as B
+    from paper_1610_00823_amd import inputs as I
+
+    t0 = time.perf_counter()
+    tree, src = I.workload(args.workload, args.n)
+    f_host = I.sample(tree, src, args.n)
+    t_inputs = time.perf_counter() - t0
+    log(f"inputs: {args.workload}: {tree.n_leaves} leaves, {f_host.size} points, {t_inputs:.1f} s")
+
+    flags = B.BX_FP64 if args.precision == "fp64" else B.BX_SPLIT_BF16
+    t0 = time.perf_counter()
+    ctx = B.Context(args.n, args.p, flags)
+    t_tables = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    tr = B.Tree.from_inputs(ctx, tree, stream)
+    f = torch.from_numpy(f_host).cuda().unsqueeze(0)
+    V = torch.empty_like(f)
+    G = torch.empty((1, tree.n_leaves, 2, args.n, args.n), dtype=torch.float64, device=f.device)
+    log(f"tables {t_tables:.1f} s, tree upload {tr.query('upload_ms'):.0f} ms")
+
+    for _ in range(args.warmup):
+        B.volume_eval_grad(ctx, tr, f, V, G, stream)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.volume_eval_grad(ctx, tr, f, V, G, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.profile(False)
+    phase_ms, nev = ctx.profile_read()
+    ms_step = dt / args.steps * 1e3
+    npts = tree.n_leaves * args.n * args.n
+    value = npts / (ms_step / 1e3)
+    per_eval = {k: v / max(nev, 1) for k, v in phase_ms.items()}
+    dom = max(per_eval, key=per_eval.get)
+    fl, by = tr.phase_cost(dom)
+    bound, peak = BOUND[dom]
+    t_dom = per_eval[dom] / 1e3
+    if bound == "hbm":
+        ach, unit, pk = by / t_dom / 1e9, "GB/s", peak / 1e9
+    else:
+        ach, unit, pk = fl / t_dom / 1e12, "TFLOP/s", peak / 1e12
+    roofline = {"bound": bound, "achieved": ach, "peak": pk, "unit": unit, "frac": ach / pk, "traffic": None,
+                "kernel": KERNEL_OF[dom], "launch_ms": per_eval[dom],
+                "algorithmic_flops": fl, "algorithmic_bytes": by}
+    phases = {}
+    for k, v in per_eval.items():
+        a, b = tr.phase_cost(k)
+        phases[k] = {"ms": round(v, 4), "tflops": round(a / (v / 1e3) / 1e12, 3) if v > 0 else None}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "leaf-points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "bf16-split+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "precision": args.precision, "n_leaves": tree.n_leaves, "points": npts, "nodes": args.n,
+                   "order": args.p, "levels": int(tr.query("n_levels")), "tree_upload_ms": tr.query("upload_ms"),
+                   "table_build_s": t_tables},
+        "roofline": roofline,
+        "phases": phases,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(tree, f_host)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -133,7 +133,24 @@ enum {
   BX_Q_FAR_FLOPS = 10,       /* algorithmic flops of P2M, M2M, M2L, W, X, L2L, L2T, one RHS */
   BX_Q_NEAR_TILES = 11,      /* 16-target tiles of the near kernel */
   BX_Q_NEAR_SLOTS = 12,      /* (tile, configuration) slots of the near kernel */
-  BX_Q_UPLOAD_MS = 13        /* host time of the last bx_tree_upload, milliseconds */
+  BX_Q_UPLOAD_MS = 13,       /* host time of the last bx_tree_upload, milliseconds */
+  /* algorithmic FP64 flops of one evaluation phase, one RHS: add the phase index */
+  BX_Q_PHASE_FLOPS = 20,
+  /* algorithmic bytes of one evaluation phase (each operand read and each result
+     written once from HBM; operator tables excluded), one RHS: add the phase index */
+  BX_Q_PHASE_BYTES = 40
+};
+
+/* Evaluation phases, in stream order. */
+enum {
+  BX_PH_P2M = 0,     /* leaf samples to multipoles */
+  BX_PH_M2M = 1,     /* upward pass, one launch per level */
+  BX_PH_M2L = 2,     /* V list: multipole to local, all levels in one launch */
+  BX_PH_P2L = 3,     /* X list: coarse leaf samples to local */
+  BX_PH_L2L = 4,     /* downward pass, one launch per level */
+  BX_PH_LEAF = 5,    /* near tables (U list), local expansions and W-list multipoles
+                        to the nodes, in one fused kernel */
+  BX_N_PHASES = 6
 };
 int bx_query(const bx_ctx *ctx, const bx_tree *tree, int what, double *out);
 
@@ -159,6 +176,17 @@ int bx_tree_list(const bx_tree *tree, int kind, int64_t *out, int64_t cap, int64
  * KP = p+1 rounded up to 16.  With out == NULL only *count is written.
  */
 int bx_table_copy(const bx_ctx *ctx, int which, double *out, int64_t cap, int64_t *count);
+
+/*
+ * Per-phase timing with HIP events recorded on the evaluation stream.
+ * bx_profile(ctx, 1) makes later evaluations record an event pair around each
+ * phase; bx_profile_read waits for the recorded events, adds their elapsed
+ * times to ms[phase] (BX_N_PHASES entries, caller-owned), writes the number of
+ * timed evaluations to *n_evals and clears the record.  Recording adds a few
+ * microseconds per phase.  Errors: BX_E_ARG, BX_E_HIP.
+ */
+int bx_profile(bx_ctx *ctx, int enable);
+int bx_profile_read(bx_ctx *ctx, double *ms, int *n_evals);
 
 void bx_tree_destroy(bx_tree *tree);
 void bx_destroy(bx_ctx *ctx);

@@ -22,9 +22,10 @@ Q = dict(n_leaves=0, n_boxes=1, n_levels=2, nodes=3, order=4, near_pairs=5, v_pa
          x_pairs=8, near_flops=9, far_flops=10, near_tiles=11, near_slots=12, upload_ms=13)
 TABLES = dict(near=0, p2m=1, m2m=2, l2l=3, m2l_core=4, m2l_src_pow=5, m2l_tgt_pow=6, logd=7, l2t=8,
               m2t=9, p2l=10, weights=11)
+PHASES = ["p2m", "m2m", "m2l", "p2l", "l2l", "leaf"]
 SYMBOLS = ["bx_create", "bx_build_tables", "bx_tree_upload", "bx_volume_eval_grad", "bx_volume_eval",
-           "bx_volume_grad", "bx_query", "bx_tree_list", "bx_table_copy", "bx_tree_destroy",
-           "bx_destroy", "bx_last_error"]
+           "bx_volume_grad", "bx_query", "bx_tree_list", "bx_table_copy", "bx_profile", "bx_profile_read",
+           "bx_tree_destroy", "bx_destroy", "bx_last_error"]
 
 _lib = None
 
@@ -58,6 +59,8 @@ def lib():
         L.bx_query.argtypes = [vp, vp, i32, ctypes.POINTER(dp)]
         L.bx_tree_list.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
         L.bx_table_copy.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
+        L.bx_profile.argtypes = [vp, i32]
+        L.bx_profile_read.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(i32)]
         L.bx_tree_destroy.argtypes = [vp]
         L.bx_destroy.argtypes = [vp]
         L.bx_last_error.restype = ctypes.c_char_p
@@ -103,6 +106,16 @@ class Context:
         _check(lib().bx_table_copy(self._h, TABLES[name], out.ctypes.data, cnt.value, ctypes.byref(cnt)))
         return out
 
+    def profile(self, enable: bool = True):
+        _check(lib().bx_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """{phase: total ms} and the number of timed evaluations since the last read."""
+        ms = (ctypes.c_double * len(PHASES))()
+        nev = ctypes.c_int()
+        _check(lib().bx_profile_read(self._h, ms, ctypes.byref(nev)))
+        return dict(zip(PHASES, list(ms))), nev.value
+
     def close(self):
         if self._h:
             lib().bx_destroy(self._h)
@@ -137,6 +150,14 @@ class Tree:
         v = ctypes.c_double()
         _check(lib().bx_query(self.ctx._h, self._h, Q[what], ctypes.byref(v)))
         return v.value
+
+    def phase_cost(self, phase: str):
+        """(algorithmic flops, algorithmic bytes) of one evaluation phase for one RHS."""
+        k = PHASES.index(phase)
+        fl, by = ctypes.c_double(), ctypes.c_double()
+        _check(lib().bx_query(self.ctx._h, self._h, 20 + k, ctypes.byref(fl)))
+        _check(lib().bx_query(self.ctx._h, self._h, 40 + k, ctypes.byref(by)))
+        return fl.value, by.value
 
     def lists(self, kind: int) -> np.ndarray:
         cnt = ctypes.c_int64()

@@ -15,6 +15,10 @@ struct bx_ctx {
   int n = 0, p = 0, device = 0;
   uint32_t flags = 0;
   bool ready = false;
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;            // recorded event pairs, phase-tagged
+  std::vector<int> ev_phase;
+  int ev_evals = 0;
   bx::Tables T;
   std::vector<void *> dev;    // device allocations owned by the context
   bx::DevTables dt{};
@@ -149,7 +153,10 @@ int bx_build_tables(bx_ctx *ctx, double quad_tol, const char *cache_dir) {
       (rc = upload(ctx->dev, T.logd, &d.logd, s)) || (rc = upload(ctx->dev, T.l2t, &d.l2t, s)) ||
       (rc = upload(ctx->dev, T.m2t, &d.m2t, s)) || (rc = upload(ctx->dev, T.p2l, &d.p2l, s)))
     return rc;
-  d.near_frag = nullptr;
+  std::vector<double> lf, pf;
+  build_leaf_frag(T, lf);
+  build_p2m_frag(T, pf);
+  if ((rc = upload(ctx->dev, lf, &d.leaf_frag, s)) || (rc = upload(ctx->dev, pf, &d.p2m_frag, s))) return rc;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "bx_build_tables: upload");
   ctx->ready = true;
@@ -181,37 +188,66 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
   csr(H.n_boxes, H.v_t, H.v_s, H.v_c, vp, vs, vc);
   csr(H.n_leaves, H.w_t, H.w_s, H.w_c, wp, ws, wc);
   csr(H.n_boxes, H.x_t, H.x_s, H.x_c, xp, xs, xc);
-  // near tiles: leaves sorted by their set of configurations, 16 per tile
+  // fused leaf GEMM tiles: leaves sorted by their set of near and W
+  // configurations, TL per tile; each tile's slots are the union of its
+  // leaves' configurations plus one L2T slot.
+  const int TL = 64;
+  const LeafFragLayout FL = leaf_frag_layout(ctx->n, ctx->p);
   std::vector<uint64_t> sig(H.n_leaves, 0);
-  for (int i = 0; i < H.n_leaves; ++i)
+  for (int i = 0; i < H.n_leaves; ++i) {
     for (int e = up[i]; e < up[i + 1]; ++e) sig[i] |= 1ull << uc[e];
+    for (int e = wp[i]; e < wp[i + 1]; ++e) sig[i] |= 1ull << (NCFG_U + wc[e]);
+  }
   std::vector<int> order(H.n_leaves);
   for (int i = 0; i < H.n_leaves; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sig[a] < sig[b]; });
-  int ntiles = (H.n_leaves + 15) / 16;
-  std::vector<int> tile_tgt((size_t)ntiles * 16, -1), tile_ptr(ntiles + 1, 0), slot_cfg, slot_src;
+  int ntiles = (H.n_leaves + TL - 1) / TL;
+  std::vector<int> tile_tgt((size_t)ntiles * TL, -1), tile_ptr(ntiles + 1, 0), slot_aoff, slot_type, slot_src;
   for (int tt = 0; tt < ntiles; ++tt) {
     uint64_t uni = 0;
-    for (int k = 0; k < 16 && tt * 16 + k < H.n_leaves; ++k) {
-      int leaf = order[tt * 16 + k];
-      tile_tgt[(size_t)tt * 16 + k] = leaf;
+    for (int k = 0; k < TL && tt * TL + k < H.n_leaves; ++k) {
+      int leaf = order[tt * TL + k];
+      tile_tgt[(size_t)tt * TL + k] = leaf;
       uni |= sig[leaf];
     }
     for (int c = 0; c < NCFG_U; ++c) {
       if (!(uni >> c & 1)) continue;
-      slot_cfg.push_back(c);
-      for (int k = 0; k < 16; ++k) {
-        int leaf = tile_tgt[(size_t)tt * 16 + k], src = -1;
+      slot_aoff.push_back((int)(FL.near0 + c * FL.near_step));
+      slot_type.push_back(0);
+      for (int k = 0; k < TL; ++k) {
+        int leaf = tile_tgt[(size_t)tt * TL + k], src = -1;
         if (leaf >= 0)
           for (int e = up[leaf]; e < up[leaf + 1]; ++e)
             if (uc[e] == c) src = us[e];
         slot_src.push_back(src);
       }
     }
-    tile_ptr[tt + 1] = (int)slot_cfg.size();
+    slot_aoff.push_back((int)FL.l2t);
+    slot_type.push_back(1);
+    for (int k = 0; k < TL; ++k) {
+      int leaf = tile_tgt[(size_t)tt * TL + k];
+      slot_src.push_back(leaf >= 0 ? H.box_of_leaf[leaf] : -1);
+    }
+    for (int c = 0; c < NCFG_W; ++c) {
+      if (!(uni >> (NCFG_U + c) & 1)) continue;
+      slot_aoff.push_back((int)(FL.w0 + c * FL.w_step));
+      slot_type.push_back(2);
+      for (int k = 0; k < TL; ++k) {
+        int leaf = tile_tgt[(size_t)tt * TL + k], src = -1;
+        if (leaf >= 0)
+          for (int e = wp[leaf]; e < wp[leaf + 1]; ++e)
+            if (wc[e] == c) src = ws[e];
+        slot_src.push_back(src);
+      }
+    }
+    tile_ptr[tt + 1] = (int)slot_type.size();
   }
   g.n_tiles = ntiles;
-  t->n_slots = (int64_t)slot_cfg.size();
+  std::vector<int> x_boxes;
+  for (int b = 0; b < H.n_boxes; ++b)
+    if (xp[b + 1] > xp[b]) x_boxes.push_back(b);
+  g.n_x_boxes = (int)x_boxes.size();
+  t->n_slots = (int64_t)slot_type.size();
   if (ctx->flags & BX_HOST_ONLY) {
     t->upload_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = t;
@@ -226,8 +262,10 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       (rc = upload(t->dev, wp, &g.w_ptr, s)) || (rc = upload(t->dev, ws, &g.w_src, s)) ||
       (rc = upload(t->dev, wc, &g.w_cfg, s)) || (rc = upload(t->dev, xp, &g.x_ptr, s)) ||
       (rc = upload(t->dev, xs, &g.x_src, s)) || (rc = upload(t->dev, xc, &g.x_cfg, s)) ||
+      (rc = upload(t->dev, x_boxes, &g.x_boxes, s)) ||
       (rc = upload(t->dev, tile_tgt, &g.tile_tgt, s)) || (rc = upload(t->dev, tile_ptr, &g.tile_ptr, s)) ||
-      (rc = upload(t->dev, slot_cfg, &g.slot_cfg, s)) || (rc = upload(t->dev, slot_src, &g.slot_src, s))) {
+      (rc = upload(t->dev, slot_aoff, &g.slot_aoff, s)) || (rc = upload(t->dev, slot_type, &g.slot_type, s)) ||
+      (rc = upload(t->dev, slot_src, &g.slot_src, s))) {
     bx_tree_destroy(t);
     return rc;
   }
@@ -270,14 +308,37 @@ static int eval_impl(bx_ctx *ctx, const bx_tree *tree_c, const double *f, int nr
   const DevTables &d = ctx->dt;
   const DevTree &g = t->dg;
   const HostTree &H = t->H;
+  hipEvent_t e0 = nullptr;
+  auto mark = [&](int phase, bool start) -> int {
+    if (!ctx->profiling) return BX_OK;
+    hipEvent_t ev;
+    hipError_t he = hipEventCreate(&ev);
+    if (he == hipSuccess) he = hipEventRecord(ev, s);
+    if (he != hipSuccess) return hip_fail(he, "profiling event");
+    if (start) {
+      e0 = ev;
+    } else {
+      ctx->ev.push_back(e0);
+      ctx->ev.push_back(ev);
+      ctx->ev_phase.push_back(phase);
+    }
+    return BX_OK;
+  };
+  if ((rc = mark(BX_PH_P2M, true))) return rc;
   launch_p2m(d, g, f, nrhs, t->M, s);
+  if ((rc = mark(BX_PH_P2M, false)) || (rc = mark(BX_PH_M2M, true))) return rc;
   for (int l = H.n_levels - 2; l >= 0; --l)
     launch_m2m(d, g, l, H.level_start[l], H.level_start[l + 1], nrhs, t->M, s);
+  if ((rc = mark(BX_PH_M2M, false)) || (rc = mark(BX_PH_M2L, true))) return rc;
   launch_m2l(d, g, nrhs, t->M, t->L, s);
+  if ((rc = mark(BX_PH_M2L, false)) || (rc = mark(BX_PH_P2L, true))) return rc;
   launch_p2l(d, g, f, nrhs, t->L, s);
+  if ((rc = mark(BX_PH_P2L, false)) || (rc = mark(BX_PH_L2L, true))) return rc;
   for (int l = 1; l < H.n_levels; ++l) launch_l2l(d, g, H.level_start[l], H.level_start[l + 1], nrhs, t->L, s);
-  launch_leaf_far(d, g, nrhs, t->M, t->L, V, G, s);
-  launch_near(d, g, f, nrhs, V, G, s);
+  if ((rc = mark(BX_PH_L2L, false)) || (rc = mark(BX_PH_LEAF, true))) return rc;
+  launch_leaf(d, g, f, nrhs, t->M, t->L, V, G, s);
+  if ((rc = mark(BX_PH_LEAF, false))) return rc;
+  if (ctx->profiling) ctx->ev_evals++;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return BX_OK;
@@ -311,6 +372,52 @@ int bx_volume_grad(bx_ctx *ctx, const bx_tree *tree, const double *f_dev, int n_
                    bx_stream_t stream) {
   if (!G_dev) return fail(BX_E_ARG, "bx_volume_grad: NULL output");
   return scratch_eval(ctx, tree, f_dev, n_rhs, nullptr, G_dev, false, stream);
+}
+
+int bx_profile(bx_ctx *ctx, int enable) {
+  if (!ctx) return fail(BX_E_ARG, "bx_profile: ctx is NULL");
+  ctx->profiling = enable != 0;
+  return BX_OK;
+}
+
+int bx_profile_read(bx_ctx *ctx, double *ms, int *n_evals) {
+  if (!ctx || !ms || !n_evals) return fail(BX_E_ARG, "bx_profile_read: NULL argument");
+  int rc = BX_OK;
+  for (size_t i = 0; i < ctx->ev_phase.size(); ++i) {
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(ctx->ev[2 * i + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, ctx->ev[2 * i], ctx->ev[2 * i + 1]);
+    if (e != hipSuccess && rc == BX_OK) rc = hip_fail(e, "bx_profile_read");
+    ms[ctx->ev_phase[i]] += t;
+  }
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  *n_evals = ctx->ev_evals;
+  ctx->ev.clear();
+  ctx->ev_phase.clear();
+  ctx->ev_evals = 0;
+  return rc;
+}
+
+// Algorithmic flops and bytes of one phase for one right-hand side.
+static void phase_cost(const bx_ctx *ctx, const HostTree &H, int ph, double *flops, double *bytes) {
+  const double P = ctx->n * ctx->n, nt = ctx->p + 1, NL = H.n_leaves, NB = H.n_boxes, C = 16.0 * nt;
+  double nint = 0;
+  for (int b = 0; b < H.n_boxes; ++b) nint += H.leaf_of_box[b] < 0;
+  double U = (double)H.u_t.size(), Vp = (double)H.v_t.size(), W = (double)H.w_t.size(),
+         X = (double)H.x_t.size();
+  *flops = *bytes = 0;
+  switch (ph) {
+    case BX_PH_P2M: *flops = 2.0 * 2 * nt * P * NL; *bytes = NL * (8 * P + C); break;
+    case BX_PH_M2M: *flops = 8.0 * nt * (nt + 1) / 2 * 4 * nint; *bytes = (4 * nint + nint) * C; break;
+    case BX_PH_M2L: *flops = Vp * (4.0 * nt * nt + 12.0 * nt); *bytes = NB * C + NB * C; break;
+    case BX_PH_P2L: *flops = X * 2.0 * 2 * nt * P; *bytes = X * 8 * P + 2 * NB * C; break;
+    case BX_PH_L2L: *flops = 8.0 * nt * (nt + 1) / 2 * (NB - 1); *bytes = (NB - 1) * 2 * C; break;
+    case BX_PH_LEAF:   // near tables (with the mass row) + L2T + W, fused
+      *flops = U * 2.0 * (3 * P + 1) * P + 2.0 * 3 * P * 2 * nt * NL + 2.0 * (3 * P + 1) * 2 * nt * W;
+      *bytes = NL * 8 * P + NL * C + NL * 24 * P;
+      break;
+    default: break;
+  }
 }
 
 int bx_query(const bx_ctx *ctx, const bx_tree *tree, int what, double *out) {
@@ -352,7 +459,18 @@ int bx_query(const bx_ctx *ctx, const bx_tree *tree, int what, double *out) {
     case BX_Q_NEAR_TILES: *out = tree->dg.n_tiles; break;
     case BX_Q_NEAR_SLOTS: *out = (double)tree->n_slots; break;
     case BX_Q_UPLOAD_MS: *out = tree->upload_ms; break;
-    default: return fail(BX_E_ARG, "bx_query: unknown quantity");
+    default: {
+      double fl, by;
+      if (what >= BX_Q_PHASE_FLOPS && what < BX_Q_PHASE_FLOPS + BX_N_PHASES) {
+        phase_cost(ctx, H, what - BX_Q_PHASE_FLOPS, &fl, &by);
+        *out = fl;
+      } else if (what >= BX_Q_PHASE_BYTES && what < BX_Q_PHASE_BYTES + BX_N_PHASES) {
+        phase_cost(ctx, H, what - BX_Q_PHASE_BYTES, &fl, &by);
+        *out = by;
+      } else {
+        return fail(BX_E_ARG, "bx_query: unknown quantity");
+      }
+    }
   }
   return BX_OK;
 }
@@ -403,6 +521,7 @@ void bx_tree_destroy(bx_tree *tree) {
 
 void bx_destroy(bx_ctx *ctx) {
   if (!ctx) return;
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   for (void *p : ctx->dev) (void)hipFree(p);
   delete ctx;
 }

@@ -44,6 +44,16 @@ struct Tables {
 };
 
 int build_tables(Tables &T, int n, int p, double tol, int nthreads);
+
+// Fragment-major A operands of the fused leaf GEMM: 33 near tables (K = P),
+// then L2T, then the 20 W operators (K = 2 KP), each MR rows.
+struct LeafFragLayout {
+  int MT, KSU, KSE;          // row tiles, k-steps of near slots, k-steps of expansion slots
+  int64_t near0, near_step, l2t, w0, w_step, total;
+};
+LeafFragLayout leaf_frag_layout(int n, int p);
+void build_leaf_frag(const Tables &T, std::vector<double> &out);
+void build_p2m_frag(const Tables &T, std::vector<double> &out);
 uint64_t tables_checksum(const Tables &T);
 bool save_tables(const Tables &T, const std::string &path);
 bool load_tables(Tables &T, const std::string &path, int n, int p);

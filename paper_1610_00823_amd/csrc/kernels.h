@@ -8,7 +8,11 @@ namespace bx {
 // Device copies of the unit-box operators (see bx_internal.h for layouts).
 struct DevTables {
   int n, P, p, nt, KP, MR;
-  const double *wq, *near_, *near_frag, *p2m, *m2m, *l2l, *H, *pw_src, *pw_tgt, *logd, *l2t, *m2t, *p2l;
+  const double *wq, *near_, *p2m, *m2m, *l2l, *H, *pw_src, *pw_tgt, *logd, *l2t, *m2t, *p2l;
+  // Fragment-major A operands of the fused leaf GEMM (near tables, L2T, W) and of P2M:
+  // frag[((op * MT + mt) * KS + ks) * 64 + lane] = A[mt*16 + lane%16][(lane/16) * KS + ks],
+  // K = 4 KS; the k index is split so that each lane's B operand is contiguous.
+  const double *leaf_frag, *p2m_frag;
 };
 
 // Device copy of a tree's hierarchy and lists (CSR by target, sorted).
@@ -27,14 +31,19 @@ struct DevTree {
   const int *v_ptr, *v_src, *v_cfg;
   // W: per target leaf, CSR of (source box, config)
   const int *w_ptr, *w_src, *w_cfg;
-  // X: per target box, CSR of (source leaf, config)
+  // X: per target box, CSR of (source leaf, config); the boxes with X entries
   const int *x_ptr, *x_src, *x_cfg;
-  // near kernel tiling: 16-target tiles, slots of (config, 16 sources)
+  int n_x_boxes;
+  const int *x_boxes;
+  // fused leaf GEMM tiling: 64-target tiles; each slot is one A operand (a near
+  // table, L2T or a W configuration) applied to 64 gathered B columns
   int n_tiles;
-  const int *tile_tgt;     // [n_tiles][16], -1 = padding
+  const int *tile_tgt;     // [n_tiles][64], -1 = padding
   const int *tile_ptr;     // [n_tiles + 1] into slots
-  const int *slot_cfg;     // [n_slots]
-  const int *slot_src;     // [n_slots][16], -1 = none
+  const int *slot_aoff;    // [n_slots] offset of the A fragments in leaf_frag
+  const int *slot_type;    // [n_slots] 0: samples f of a source leaf (K = P); 1: local expansion
+                           // of the target's box; 2: multipole of a source box (K = 2 KP)
+  const int *slot_src;     // [n_slots][64] leaf or box index, -1 = none
 };
 
 // Expansion storage: [n_rhs][NB][KP] complex (interleaved re, im).
@@ -44,9 +53,8 @@ void launch_m2m(const DevTables &t, const DevTree &g, int level, int box0, int b
 void launch_m2l(const DevTables &t, const DevTree &g, int nrhs, const double *M, double *L, hipStream_t s);
 void launch_p2l(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *L, hipStream_t s);
 void launch_l2l(const DevTables &t, const DevTree &g, int box0, int box1, int nrhs, double *L, hipStream_t s);
-void launch_leaf_far(const DevTables &t, const DevTree &g, int nrhs, const double *M, const double *L, double *V,
-                     double *G, hipStream_t s);
-void launch_near(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *V, double *G,
-                 hipStream_t s);
+// Near tables + L2T + W list for every leaf: writes V and G.
+void launch_leaf(const DevTables &t, const DevTree &g, const double *f, int nrhs, const double *M,
+                 const double *L, double *V, double *G, hipStream_t s);
 
 }  // namespace bx

@@ -468,6 +468,68 @@ int build_tables(Tables &T, int n, int p, double tol, int nthreads) {
   return BX_OK;
 }
 
+LeafFragLayout leaf_frag_layout(int n, int p) {
+  LeafFragLayout L;
+  const int P = n * n, KP = (p + 1 + 15) / 16 * 16, MR = (3 * P + 1 + 15) / 16 * 16;
+  L.MT = MR / 16;
+  L.KSU = P / 4;
+  L.KSE = 2 * KP / 4;
+  L.near0 = 0;
+  L.near_step = (int64_t)L.MT * L.KSU * 64;
+  L.l2t = L.near0 + NCFG_U * L.near_step;
+  L.w_step = (int64_t)L.MT * L.KSE * 64;
+  L.w0 = L.l2t + L.w_step;
+  L.total = L.w0 + NCFG_W * L.w_step;
+  return L;
+}
+
+namespace {
+// Append the MFMA A fragments of a rows x K matrix (element (i, k) = a(i, k)),
+// row tiles of 16 and k split as k = (lane / 16) * KS + ks.
+template <class F>
+void append_frag(std::vector<double> &out, int MT, int K, F a) {
+  const int KS = K / 4;
+  for (int mt = 0; mt < MT; ++mt)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int lane = 0; lane < 64; ++lane) out.push_back(a(mt * 16 + (lane & 15), (lane >> 4) * KS + ks));
+}
+}  // namespace
+
+void build_leaf_frag(const Tables &T, std::vector<double> &out) {
+  const LeafFragLayout L = leaf_frag_layout(T.n, T.p);
+  const int P = T.P, KP = T.KP, MR = T.MR;
+  out.clear();
+  out.reserve(L.total);
+  for (int c = 0; c < NCFG_U; ++c) {
+    const double *A = &T.near_[(size_t)c * MR * P];
+    append_frag(out, L.MT, P, [&](int i, int k) { return A[(size_t)i * P + k]; });
+  }
+  // expansion columns are stored interleaved (Re b_m, Im b_m) as in device memory
+  append_frag(out, L.MT, 2 * KP, [&](int i, int k) {
+    if (i >= 3 * P) return 0.0;
+    return T.l2t[(size_t)i * 2 * KP + (k & 1) * KP + k / 2];
+  });
+  // W: V rows carry log|e| - log 2 in the a_0 column (log(h/2) = log h - log 2, the
+  // log h part comes through the mass row), gradient rows are doubled (1/(h/2)).
+  const double log2_2pi = std::log(2.0) / (2 * 3.14159265358979323846);
+  for (int c = 0; c < NCFG_W; ++c) {
+    const double *A = &T.m2t[(size_t)c * 3 * P * 2 * KP];
+    append_frag(out, L.MT, 2 * KP, [&](int i, int k) {
+      if (i == 3 * P) return k == 0 ? 1.0 : 0.0;
+      if (i > 3 * P) return 0.0;
+      double v = A[(size_t)i * 2 * KP + (k & 1) * KP + k / 2];
+      if (i < P && k == 0) v -= log2_2pi;
+      if (i >= P) v *= 2.0;
+      return v;
+    });
+  }
+}
+
+void build_p2m_frag(const Tables &T, std::vector<double> &out) {
+  out.clear();
+  append_frag(out, 2 * T.KP / 16, T.P, [&](int i, int k) { return T.p2m[(size_t)i * T.P + k]; });
+}
+
 uint64_t tables_checksum(const Tables &T) {
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](const std::vector<double> &v) {
