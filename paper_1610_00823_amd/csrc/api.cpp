@@ -19,14 +19,26 @@ struct bx_ctx {
   std::vector<hipEvent_t> ev;            // recorded event pairs, phase-tagged
   std::vector<int> ev_phase;
   int ev_evals = 0;
+  hipStream_t capture_stream = nullptr;  // private stream used only to capture graphs
   bx::Tables T;
   std::vector<void *> dev;    // device allocations owned by the context
   bx::DevTables dt{};
 };
 
+struct GraphEntry {
+  const double *f = nullptr;
+  double *V = nullptr, *G = nullptr;
+  int nrhs = 0;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct bx_tree {
   bx_ctx *ctx = nullptr;
+  GraphEntry graphs[4];                  // captured evaluations, keyed by (f, V, G, n_rhs)
+  int graph_next = 0;
   bx::HostTree H;
+  std::vector<int> int_start;            // per level: offset of its internal boxes in int_boxes
+  const int *int_boxes = nullptr;        // device
   std::vector<void *> dev;
   bx::DevTree dg{};
   double *M = nullptr, *L = nullptr;   // expansions, grown with n_rhs
@@ -153,10 +165,16 @@ int bx_build_tables(bx_ctx *ctx, double quad_tol, const char *cache_dir) {
       (rc = upload(ctx->dev, T.logd, &d.logd, s)) || (rc = upload(ctx->dev, T.l2t, &d.l2t, s)) ||
       (rc = upload(ctx->dev, T.m2t, &d.m2t, s)) || (rc = upload(ctx->dev, T.p2l, &d.p2l, s)))
     return rc;
-  std::vector<double> lf, pf;
+  std::vector<double> lf, pf, mf, llf, xf;
   build_leaf_frag(T, lf);
   build_p2m_frag(T, pf);
-  if ((rc = upload(ctx->dev, lf, &d.leaf_frag, s)) || (rc = upload(ctx->dev, pf, &d.p2m_frag, s))) return rc;
+  build_m2m_frag(T, mf);
+  build_l2l_frag(T, llf);
+  build_p2l_frag(T, xf);
+  if ((rc = upload(ctx->dev, lf, &d.leaf_frag, s)) || (rc = upload(ctx->dev, pf, &d.p2m_frag, s)) ||
+      (rc = upload(ctx->dev, mf, &d.m2m_frag, s)) || (rc = upload(ctx->dev, llf, &d.l2l_frag, s)) ||
+      (rc = upload(ctx->dev, xf, &d.p2l_frag, s)))
+    return rc;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "bx_build_tables: upload");
   ctx->ready = true;
@@ -243,10 +261,46 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
     tile_ptr[tt + 1] = (int)slot_type.size();
   }
   g.n_tiles = ntiles;
-  std::vector<int> x_boxes;
+  // X-list tiles: target boxes with X entries, sorted by configuration set
+  std::vector<int> xb;
+  std::vector<uint32_t> xsig(H.n_boxes, 0);
   for (int b = 0; b < H.n_boxes; ++b)
-    if (xp[b + 1] > xp[b]) x_boxes.push_back(b);
-  g.n_x_boxes = (int)x_boxes.size();
+    if (xp[b + 1] > xp[b]) {
+      xb.push_back(b);
+      for (int e = xp[b]; e < xp[b + 1]; ++e) xsig[b] |= 1u << xc[e];
+    }
+  std::stable_sort(xb.begin(), xb.end(), [&](int a, int b) { return xsig[a] < xsig[b]; });
+  const int nxt = ((int)xb.size() + 15) / 16;
+  std::vector<int> xtile_box((size_t)nxt * 16, -1), xtile_ptr(nxt + 1, 0), xslot_cfg, xslot_src;
+  for (int tt = 0; tt < nxt; ++tt) {
+    uint32_t uni = 0;
+    for (int k = 0; k < 16 && tt * 16 + k < (int)xb.size(); ++k) {
+      xtile_box[(size_t)tt * 16 + k] = xb[tt * 16 + k];
+      uni |= xsig[xb[tt * 16 + k]];
+    }
+    for (int c = 0; c < NCFG_X; ++c) {
+      if (!(uni >> c & 1)) continue;
+      xslot_cfg.push_back(c);
+      for (int k = 0; k < 16; ++k) {
+        int b = xtile_box[(size_t)tt * 16 + k], src = -1;
+        if (b >= 0)
+          for (int e = xp[b]; e < xp[b + 1]; ++e)
+            if (xc[e] == c) src = xs[e];
+        xslot_src.push_back(src);
+      }
+    }
+    xtile_ptr[tt + 1] = (int)xslot_cfg.size();
+  }
+  g.n_xtiles = nxt;
+  // internal boxes of each level (the M2M targets and the L2L sources)
+  t->int_start.assign(H.n_levels + 1, 0);
+  std::vector<int> ib;
+  for (int l = 0; l < H.n_levels; ++l) {
+    t->int_start[l] = (int)ib.size();
+    for (int b = H.level_start[l]; b < H.level_start[l + 1]; ++b)
+      if (H.leaf_of_box[b] < 0) ib.push_back(b);
+  }
+  t->int_start[H.n_levels] = (int)ib.size();
   t->n_slots = (int64_t)slot_type.size();
   if (ctx->flags & BX_HOST_ONLY) {
     t->upload_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -262,7 +316,9 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       (rc = upload(t->dev, wp, &g.w_ptr, s)) || (rc = upload(t->dev, ws, &g.w_src, s)) ||
       (rc = upload(t->dev, wc, &g.w_cfg, s)) || (rc = upload(t->dev, xp, &g.x_ptr, s)) ||
       (rc = upload(t->dev, xs, &g.x_src, s)) || (rc = upload(t->dev, xc, &g.x_cfg, s)) ||
-      (rc = upload(t->dev, x_boxes, &g.x_boxes, s)) ||
+      (rc = upload(t->dev, xtile_box, &g.xtile_box, s)) || (rc = upload(t->dev, xtile_ptr, &g.xtile_ptr, s)) ||
+      (rc = upload(t->dev, xslot_cfg, &g.xslot_cfg, s)) || (rc = upload(t->dev, xslot_src, &g.xslot_src, s)) ||
+      (rc = upload(t->dev, ib, &t->int_boxes, s)) ||
       (rc = upload(t->dev, tile_tgt, &g.tile_tgt, s)) || (rc = upload(t->dev, tile_ptr, &g.tile_ptr, s)) ||
       (rc = upload(t->dev, slot_aoff, &g.slot_aoff, s)) || (rc = upload(t->dev, slot_type, &g.slot_type, s)) ||
       (rc = upload(t->dev, slot_src, &g.slot_src, s))) {
@@ -280,8 +336,16 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
   return BX_OK;
 }
 
+static void drop_graphs(bx_tree *t) {
+  for (GraphEntry &e : t->graphs) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    e = GraphEntry();
+  }
+}
+
 static int ensure_expansions(bx_tree *t, int nrhs) {
   if (t->exp_rhs >= nrhs) return BX_OK;
+  drop_graphs(t);
   if (t->M) (void)hipFree(t->M);
   if (t->L) (void)hipFree(t->L);
   t->M = t->L = nullptr;
@@ -294,20 +358,12 @@ static int ensure_expansions(bx_tree *t, int nrhs) {
   return BX_OK;
 }
 
-static int eval_impl(bx_ctx *ctx, const bx_tree *tree_c, const double *f, int nrhs, double *V, double *G,
-                     bx_stream_t stream) {
-  if (!ctx || !tree_c || !f || nrhs <= 0) return fail(BX_E_ARG, "volume eval: NULL argument or n_rhs <= 0");
-  if (!ctx->ready) return fail(BX_E_NO_TABLES, "volume eval: bx_build_tables has not been called");
-  if (ctx->flags & BX_HOST_ONLY) return fail(BX_E_UNSUPPORTED, "volume eval: host-only context");
-  bx_tree *t = const_cast<bx_tree *>(tree_c);
-  if (t->ctx != ctx) return fail(BX_E_ARG, "volume eval: tree belongs to another context");
-  if (((uintptr_t)f | (uintptr_t)V | (uintptr_t)G) & 7) return fail(BX_E_ARG, "volume eval: misaligned pointer");
-  int rc = ensure_expansions(t, nrhs);
-  if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
+// Enqueue one evaluation on stream s (phases in order; per-phase events when profiling).
+static int enqueue_eval(bx_ctx *ctx, bx_tree *t, const double *f, int nrhs, double *V, double *G, hipStream_t s) {
   const DevTables &d = ctx->dt;
   const DevTree &g = t->dg;
   const HostTree &H = t->H;
+  int rc = BX_OK;
   hipEvent_t e0 = nullptr;
   auto mark = [&](int phase, bool start) -> int {
     if (!ctx->profiling) return BX_OK;
@@ -328,13 +384,14 @@ static int eval_impl(bx_ctx *ctx, const bx_tree *tree_c, const double *f, int nr
   launch_p2m(d, g, f, nrhs, t->M, s);
   if ((rc = mark(BX_PH_P2M, false)) || (rc = mark(BX_PH_M2M, true))) return rc;
   for (int l = H.n_levels - 2; l >= 0; --l)
-    launch_m2m(d, g, l, H.level_start[l], H.level_start[l + 1], nrhs, t->M, s);
+    launch_m2m(d, g, t->int_boxes + t->int_start[l], t->int_start[l + 1] - t->int_start[l], nrhs, t->M, s);
   if ((rc = mark(BX_PH_M2M, false)) || (rc = mark(BX_PH_M2L, true))) return rc;
   launch_m2l(d, g, nrhs, t->M, t->L, s);
   if ((rc = mark(BX_PH_M2L, false)) || (rc = mark(BX_PH_P2L, true))) return rc;
   launch_p2l(d, g, f, nrhs, t->L, s);
   if ((rc = mark(BX_PH_P2L, false)) || (rc = mark(BX_PH_L2L, true))) return rc;
-  for (int l = 1; l < H.n_levels; ++l) launch_l2l(d, g, H.level_start[l], H.level_start[l + 1], nrhs, t->L, s);
+  for (int l = 0; l + 1 < H.n_levels; ++l)
+    launch_l2l(d, g, t->int_boxes + t->int_start[l], t->int_start[l + 1] - t->int_start[l], nrhs, t->L, s);
   if ((rc = mark(BX_PH_L2L, false)) || (rc = mark(BX_PH_LEAF, true))) return rc;
   launch_leaf(d, g, f, nrhs, t->M, t->L, V, G, s);
   if ((rc = mark(BX_PH_LEAF, false))) return rc;
@@ -342,6 +399,51 @@ static int eval_impl(bx_ctx *ctx, const bx_tree *tree_c, const double *f, int nr
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return BX_OK;
+}
+
+static int eval_impl(bx_ctx *ctx, const bx_tree *tree_c, const double *f, int nrhs, double *V, double *G,
+                     bx_stream_t stream) {
+  if (!ctx || !tree_c || !f || nrhs <= 0) return fail(BX_E_ARG, "volume eval: NULL argument or n_rhs <= 0");
+  if (!ctx->ready) return fail(BX_E_NO_TABLES, "volume eval: bx_build_tables has not been called");
+  if (ctx->flags & BX_HOST_ONLY) return fail(BX_E_UNSUPPORTED, "volume eval: host-only context");
+  bx_tree *t = const_cast<bx_tree *>(tree_c);
+  if (t->ctx != ctx) return fail(BX_E_ARG, "volume eval: tree belongs to another context");
+  if (((uintptr_t)f | (uintptr_t)V | (uintptr_t)G) & 7) return fail(BX_E_ARG, "volume eval: misaligned pointer");
+  int rc = ensure_expansions(t, nrhs);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (ctx->profiling) return enqueue_eval(ctx, t, f, nrhs, V, G, s);
+  // replay a captured graph of the whole evaluation when the buffers match
+  for (GraphEntry &e : t->graphs)
+    if (e.exec && e.f == f && e.V == V && e.G == G && e.nrhs == nrhs) {
+      hipError_t he = hipGraphLaunch(e.exec, s);
+      return he == hipSuccess ? BX_OK : hip_fail(he, "hipGraphLaunch");
+    }
+  if (!ctx->capture_stream) {
+    hipError_t he = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+    if (he != hipSuccess) return hip_fail(he, "hipStreamCreateWithFlags");
+  }
+  hipStream_t cs = ctx->capture_stream;
+  hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (he != hipSuccess) return hip_fail(he, "hipStreamBeginCapture");
+  rc = enqueue_eval(ctx, t, f, nrhs, V, G, cs);
+  hipGraph_t graph = nullptr;
+  he = hipStreamEndCapture(cs, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (he != hipSuccess) return hip_fail(he, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (he != hipSuccess) return hip_fail(he, "hipGraphInstantiate");
+  GraphEntry &slot = t->graphs[t->graph_next];
+  t->graph_next = (t->graph_next + 1) % 4;
+  if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+  slot.f = f; slot.V = V; slot.G = G; slot.nrhs = nrhs; slot.exec = exec;
+  he = hipGraphLaunch(exec, s);
+  return he == hipSuccess ? BX_OK : hip_fail(he, "hipGraphLaunch");
 }
 
 int bx_volume_eval_grad(bx_ctx *ctx, const bx_tree *tree, const double *f_dev, int n_rhs, double *V_dev,
@@ -513,6 +615,7 @@ int bx_tree_list(const bx_tree *tree, int kind, int64_t *out, int64_t cap, int64
 
 void bx_tree_destroy(bx_tree *tree) {
   if (!tree) return;
+  drop_graphs(tree);
   for (void *p : tree->dev) (void)hipFree(p);
   if (tree->M) (void)hipFree(tree->M);
   if (tree->L) (void)hipFree(tree->L);
@@ -521,6 +624,7 @@ void bx_tree_destroy(bx_tree *tree) {
 
 void bx_destroy(bx_ctx *ctx) {
   if (!ctx) return;
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   for (void *p : ctx->dev) (void)hipFree(p);
   delete ctx;

@@ -54,6 +54,11 @@ struct LeafFragLayout {
 LeafFragLayout leaf_frag_layout(int n, int p);
 void build_leaf_frag(const Tables &T, std::vector<double> &out);
 void build_p2m_frag(const Tables &T, std::vector<double> &out);
+// M2M 4 x [2KP][2KP], L2L 4 x [2KP][2KP] on interleaved coefficients, and the
+// 20 P2L operators [2KP + mass row, padded to 16][P], fragment-major.
+void build_m2m_frag(const Tables &T, std::vector<double> &out);
+void build_l2l_frag(const Tables &T, std::vector<double> &out);
+void build_p2l_frag(const Tables &T, std::vector<double> &out);
 uint64_t tables_checksum(const Tables &T);
 bool save_tables(const Tables &T, const std::string &path);
 bool load_tables(Tables &T, const std::string &path, int n, int p);

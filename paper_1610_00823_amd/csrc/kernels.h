@@ -13,6 +13,9 @@ struct DevTables {
   // frag[((op * MT + mt) * KS + ks) * 64 + lane] = A[mt*16 + lane%16][(lane/16) * KS + ks],
   // K = 4 KS; the k index is split so that each lane's B operand is contiguous.
   const double *leaf_frag, *p2m_frag;
+  // M2M 4 x [2KP][2KP] and L2L 4 x [2KP][2KP] on interleaved coefficients, and
+  // P2L per X configuration [2KP + mass row, padded][P], all fragment-major.
+  const double *m2m_frag, *l2l_frag, *p2l_frag;
 };
 
 // Device copy of a tree's hierarchy and lists (CSR by target, sorted).
@@ -31,10 +34,14 @@ struct DevTree {
   const int *v_ptr, *v_src, *v_cfg;
   // W: per target leaf, CSR of (source box, config)
   const int *w_ptr, *w_src, *w_cfg;
-  // X: per target box, CSR of (source leaf, config); the boxes with X entries
+  // X: per target box, CSR of (source leaf, config)
   const int *x_ptr, *x_src, *x_cfg;
-  int n_x_boxes;
-  const int *x_boxes;
+  // X-list GEMM tiles: 16 target boxes per tile, slots = union of X configurations
+  int n_xtiles;
+  const int *xtile_box;    // [n_xtiles][16], -1 = padding
+  const int *xtile_ptr;    // [n_xtiles + 1]
+  const int *xslot_cfg;    // [n_xslots]
+  const int *xslot_src;    // [n_xslots][16] source leaf, -1 = none
   // fused leaf GEMM tiling: 64-target tiles; each slot is one A operand (a near
   // table, L2T or a W configuration) applied to 64 gathered B columns
   int n_tiles;
@@ -48,11 +55,14 @@ struct DevTree {
 
 // Expansion storage: [n_rhs][NB][KP] complex (interleaved re, im).
 void launch_p2m(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *M, hipStream_t s);
-void launch_m2m(const DevTables &t, const DevTree &g, int level, int box0, int box1, int nrhs, double *M,
+// Upward pass step for the internal boxes `boxes` of one level.
+void launch_m2m(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *M,
                 hipStream_t s);
 void launch_m2l(const DevTables &t, const DevTree &g, int nrhs, const double *M, double *L, hipStream_t s);
 void launch_p2l(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *L, hipStream_t s);
-void launch_l2l(const DevTables &t, const DevTree &g, int box0, int box1, int nrhs, double *L, hipStream_t s);
+// Downward pass step from the internal boxes `boxes` of one level to their children.
+void launch_l2l(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *L,
+                hipStream_t s);
 // Near tables + L2T + W list for every leaf: writes V and G.
 void launch_leaf(const DevTables &t, const DevTree &g, const double *f, int nrhs, const double *M,
                  const double *L, double *V, double *G, hipStream_t s);

@@ -16,99 +16,6 @@ constexpr double kInv2Pi = 0.15915494309189533577;
 
 __device__ inline double box_h(double width, int level) { return ldexp(width, -level); }
 
-// ------------------------------------------------------------------ M2M
-// parent from its four children, one block per (box at this level, rhs).
-__global__ void __launch_bounds__(64) m2m_kernel(DevTables t, DevTree g, int box0, double *__restrict__ M) {
-  __shared__ double cs[4 * 64 * 2];
-  const int box = box0 + blockIdx.x, rhs = blockIdx.y;
-  const int c0 = g.child0[box];
-  if (c0 < 0) return;
-  double *Mr = M + (size_t)rhs * g.n_boxes * t.KP * 2;
-  for (int i = threadIdx.x; i < 4 * t.KP * 2; i += blockDim.x) {
-    int c = i / (t.KP * 2), r = i % (t.KP * 2);
-    cs[i] = Mr[(size_t)(c0 + c) * t.KP * 2 + r];
-  }
-  __syncthreads();
-  for (int l = threadIdx.x; l < t.KP; l += blockDim.x) {
-    double re = 0.0, im = 0.0;
-    if (l < t.nt)
-      for (int c = 0; c < 4; ++c) {
-        const double *op = t.m2m + ((size_t)c * t.nt + l) * t.nt * 2;
-        const double *a = cs + c * t.KP * 2;
-        for (int k = 0; k <= l; ++k) {
-          double orr = op[2 * k], oi = op[2 * k + 1], ar = a[2 * k], ai = a[2 * k + 1];
-          re += orr * ar - oi * ai;
-          im += orr * ai + oi * ar;
-        }
-      }
-    Mr[(size_t)box * t.KP * 2 + 2 * l] = re;
-    Mr[(size_t)box * t.KP * 2 + 2 * l + 1] = im;
-  }
-}
-
-// ------------------------------------------------------------------ P2L
-// X list: b~ += h^2 * P2L_c * f_s, b~_0 += h^2 log h * 4 (W . f_s).
-__global__ void __launch_bounds__(64) p2l_kernel(DevTables t, DevTree g, const double *__restrict__ f,
-                                                 double *__restrict__ L) {
-  __shared__ double fs[256];
-  const int box = g.x_boxes[blockIdx.x], rhs = blockIdx.y;
-  const int e0 = g.x_ptr[box], e1 = g.x_ptr[box + 1];
-  if (e0 == e1) return;
-  const double h = box_h(g.width, g.lvl[box]), h2 = h * h;
-  double re[2] = {0.0, 0.0}, im[2] = {0.0, 0.0}, mass = 0.0;
-  for (int e = e0; e < e1; ++e) {
-    const int s = g.x_src[e], c = g.x_cfg[e];
-    const double *fl = f + ((size_t)rhs * g.n_leaves + s) * t.P;
-    for (int j = threadIdx.x; j < t.P; j += blockDim.x) fs[j] = fl[j];
-    __syncthreads();
-    for (int q = 0; q < 2; ++q) {
-      int l = threadIdx.x + q * blockDim.x;
-      if (l < t.nt) {
-        const double *ar = t.p2l + ((size_t)c * 2 * t.KP + l) * t.P;
-        const double *ai = t.p2l + ((size_t)c * 2 * t.KP + t.KP + l) * t.P;
-        for (int j = 0; j < t.P; ++j) {
-          re[q] = fma(ar[j], fs[j], re[q]);
-          im[q] = fma(ai[j], fs[j], im[q]);
-        }
-      }
-    }
-    if (threadIdx.x == 0)
-      for (int j = 0; j < t.P; ++j) mass = fma(t.wq[j], fs[j], mass);
-    __syncthreads();
-  }
-  double *Lb = L + ((size_t)rhs * g.n_boxes + box) * t.KP * 2;
-  for (int q = 0; q < 2; ++q) {
-    int l = threadIdx.x + q * blockDim.x;
-    if (l < t.nt) {
-      Lb[2 * l] += h2 * re[q] + (l == 0 ? 4.0 * h2 * log(h) * mass : 0.0);
-      Lb[2 * l + 1] += h2 * im[q];
-    }
-  }
-}
-
-// ------------------------------------------------------------------ L2L
-__global__ void __launch_bounds__(64) l2l_kernel(DevTables t, DevTree g, int box0, double *__restrict__ L) {
-  __shared__ double ps[64 * 2];
-  const int box = box0 + blockIdx.x, rhs = blockIdx.y;
-  const int par = g.parent[box];
-  const int c = box - g.child0[par];
-  double *Lr = L + (size_t)rhs * g.n_boxes * t.KP * 2;
-  for (int i = threadIdx.x; i < t.KP * 2; i += blockDim.x) ps[i] = Lr[(size_t)par * t.KP * 2 + i];
-  __syncthreads();
-  for (int m = threadIdx.x; m < t.nt; m += blockDim.x) {
-    const double *op = t.l2l + ((size_t)c * t.nt + m) * t.nt * 2;
-    double re = 0.0, im = 0.0;
-    for (int l = m; l < t.nt; ++l) {
-      double orr = op[2 * l], oi = op[2 * l + 1], br = ps[2 * l], bi = ps[2 * l + 1];
-      re += orr * br - oi * bi;
-      im += orr * bi + oi * br;
-    }
-    Lr[(size_t)box * t.KP * 2 + 2 * m] += re;
-    Lr[(size_t)box * t.KP * 2 + 2 * m + 1] += im;
-  }
-}
-
-
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // FP64 MFMA 16x16x4 on gfx950.  Operand layouts (one value per lane):
@@ -116,6 +23,122 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 //   register r of lane l holds D[4 r + l / 16][l % 16].
 __device__ inline dbl4 mfma4(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+
+// ------------------------------------------------- M2M, L2L and P2L GEMMs
+// Complex operators act on interleaved (Re, Im) coefficient vectors as real
+// matrices; 16 boxes per wave, A fragments streamed from the operator table
+// (k split as k = (lane / 16) * KS + ks so that each lane's B run is contiguous).
+
+// M2M for the internal boxes of one level, 16 parents per block: wave c
+// applies the operator of child position c (2KP x 2KP, on interleaved
+// coefficients) to the children at c, and the four partial results are summed
+// in LDS in a fixed order.
+template <int KPT>
+__global__ void __launch_bounds__(256) m2m_mfma_kernel(DevTables t, DevTree g, const int *__restrict__ boxes,
+                                                       int nbox, double *__restrict__ M) {
+  constexpr int R = 2 * KPT, MT = R / 16, KS = R / 4;
+  __shared__ double part[4][16][R + 1];
+  const int lane = threadIdx.x & 63, c = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
+  const int i = blockIdx.x * 16 + col, rhs = blockIdx.y;
+  const bool ok = i < nbox;
+  const int box = ok ? boxes[i] : 0;
+  double *Mr = M + (size_t)rhs * g.n_boxes * R;
+  const double *bp = Mr + (size_t)((ok ? g.child0[box] : 0) + c) * R + kq * KS;
+  const double *A = t.m2m_frag + (size_t)c * MT * KS * 64;
+  dbl4 acc[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) acc[m] = dbl4{0, 0, 0, 0};
+  for (int ks = 0; ks < KS; ks += 4) {
+    double bv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bv[j] = ok ? bp[ks + j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int m = 0; m < MT; ++m) acc[m] = mfma4(A[((size_t)m * KS + ks + j) * 64 + lane], bv[j], acc[m]);
+  }
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[c][col][m * 16 + 4 * r + kq] = acc[m][r];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 16 * R; e += 256) {
+    const int cc = e / R, row = e % R, ii = blockIdx.x * 16 + cc;
+    if (ii < nbox)
+      Mr[(size_t)boxes[ii] * R + row] = ((part[0][cc][row] + part[1][cc][row]) + part[2][cc][row]) + part[3][cc][row];
+  }
+}
+
+// L2L from the internal boxes of one level to their children at position
+// c = blockIdx.z: A = L2L_c (2KP x 2KP), B = the parent's local expansion; wave
+// w computes row tile w (of MT), so each wave's chain is short.  The result is
+// added to the child's local expansion.
+template <int KPT>
+__global__ void __launch_bounds__(256) l2l_mfma_kernel(DevTables t, DevTree g, const int *__restrict__ boxes,
+                                                       int nbox, double *__restrict__ L) {
+  constexpr int R = 2 * KPT, MT = R / 16, KS = R / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
+  const int i = blockIdx.x * 16 + col, rhs = blockIdx.y, c = blockIdx.z;
+  const bool ok = i < nbox;
+  const int box = ok ? boxes[i] : 0;
+  double *Lr = L + (size_t)rhs * g.n_boxes * R;
+  const double *bp = Lr + (size_t)box * R + kq * KS;
+  const double *A = t.l2l_frag + (size_t)c * MT * KS * 64;
+  for (int m = wave; m < MT; m += 4) {
+    dbl4 acc = dbl4{0, 0, 0, 0};
+#pragma unroll 4
+    for (int ks = 0; ks < KS; ++ks) acc = mfma4(A[((size_t)m * KS + ks) * 64 + lane], ok ? bp[ks] : 0.0, acc);
+    if (ok) {
+      double *Lc = Lr + (size_t)(g.child0[box] + c) * R;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Lc[m * 16 + 4 * r + kq] += acc[r];
+    }
+  }
+}
+
+// X list: b~ += h^2 P2L_c f_s, b~_0 += h^2 log h (4 W . f_s), over 16-box tiles
+// whose slots are the union of their X configurations (rows: 2KP interleaved
+// coefficients, then the mass row).
+template <int KPT>
+__global__ void __launch_bounds__(256) p2l_mfma_kernel(DevTables t, DevTree g, const double *__restrict__ f,
+                                                       double *__restrict__ L) {
+  constexpr int R = 2 * KPT, MT = (R + 16) / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
+  const int tile = blockIdx.x * 4 + wave;
+  if (tile >= g.n_xtiles) return;
+  const int rhs = blockIdx.y, P = t.P, KS = P / 4;
+  const int box = g.xtile_box[tile * 16 + col];
+  const double *fr = f + (size_t)rhs * g.n_leaves * P;
+  dbl4 acc[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) acc[m] = dbl4{0, 0, 0, 0};
+  for (int sl = g.xtile_ptr[tile]; sl < g.xtile_ptr[tile + 1]; ++sl) {
+    const int src = g.xslot_src[sl * 16 + col];
+    const double *A = t.p2l_frag + (size_t)g.xslot_cfg[sl] * MT * KS * 64;
+    const double *bp = fr + (size_t)(src >= 0 ? src : 0) * P + kq * KS;
+    for (int ks = 0; ks < KS; ks += 4) {
+      double bv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = src >= 0 ? bp[ks + j] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m] = mfma4(A[((size_t)m * KS + ks + j) * 64 + lane], bv[j], acc[m]);
+    }
+  }
+  const double mass = __shfl(acc[R / 16][0], col);    // mass row R: tile R/16, register 0, lanes 0..15
+  if (box < 0) return;
+  const double h = box_h(g.width, g.lvl[box]), h2 = h * h;
+  double *Lb = L + ((size_t)rhs * g.n_boxes + box) * R;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = m * 16 + 4 * r + kq;
+      if (row < R) Lb[row] += h2 * acc[m][r] + (row == 0 ? h2 * log(h) * mass : 0.0);
+    }
 }
 
 // ------------------------------------------------------------------ P2M
@@ -260,6 +283,51 @@ __device__ inline int xcd_block(int b, int nb_logical) {
   return l < nb_logical ? l : -1;
 }
 
+template <int PER>
+struct LeafStage {
+  double v[PER];
+};
+
+// This thread's share of one chunk of A fragments (4 k-steps of every staged
+// row tile; tile i < MTG is row tile mt0 + i, tile MTG the mass row's tile).
+template <int MTG, int PER>
+__device__ __forceinline__ LeafStage<PER> leaf_stage_load(const double *__restrict__ leaf_frag,
+                                                          const int *__restrict__ slot_type,
+                                                          const int *__restrict__ slot_aoff, int sl, int ks0,
+                                                          int P, int K2, int mt0, int MT, int mass_mt,
+                                                          bool extra_mass) {
+  constexpr int CH = (MTG + 1) * 4 * 64;
+  const int KS = (slot_type[sl] == 0 ? P : K2) / 4;
+  const double *A = leaf_frag + slot_aoff[sl];
+  LeafStage<PER> st;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = threadIdx.x + q * 256;
+    double v = 0.0;
+    if (idx < CH) {
+      const int i = idx / 256, j = (idx / 64) & 3, ln = idx & 63;
+      const int mt = i < MTG ? mt0 + i : mass_mt;
+      if (mt < MT && (i < MTG || extra_mass)) v = A[((size_t)mt * KS + ks0 + j) * 64 + ln];
+    }
+    st.v[q] = v;
+  }
+  return st;
+}
+
+// B operand of chunk (slot, ks0) for this lane: 4 consecutive k of its column
+// (slot_src already offset to the lane's column).
+__device__ __forceinline__ dbl4 leaf_b_load(const int *__restrict__ slot_type, const int *__restrict__ slot_src,
+                                            const double *fr, const double *Lr, const double *Mr, int sl, int ks0,
+                                            int P, int K2, int kq, double inv_h2) {
+  const int type = slot_type[sl], src = slot_src[sl * LEAF_TILE];
+  const int KS = (type == 0 ? P : K2) / 4;
+  const double *bp = type == 0 ? fr + (size_t)(src >= 0 ? src : 0) * P
+                               : (type == 1 ? Lr : Mr) + (size_t)(src >= 0 ? src : 0) * K2;
+  const double sc = src < 0 ? 0.0 : (type == 0 ? 1.0 : inv_h2);
+  const double *q = bp + kq * KS + ks0;
+  return dbl4{sc * q[0], sc * q[1], sc * q[2], sc * q[3]};
+}
+
 template <int MTG>
 __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree g, const double *__restrict__ f,
                                                            const double *__restrict__ M,
@@ -281,52 +349,36 @@ __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree 
   const int s0 = g.tile_ptr[tile], s1 = g.tile_ptr[tile + 1];
   const double *fr = f + (size_t)rhs * g.n_leaves * P;
   const double *Lr = L + (size_t)rhs * g.n_boxes * K2, *Mr = M + (size_t)rhs * g.n_boxes * K2;
-
-  // staged tile i of a chunk: group tile mt0 + i (i < MTG), else the mass tile
-  auto stage_load = [&](int sl, int ks0, double *reg) {
-    const int K = g.slot_type[sl] == 0 ? P : K2, KS = K / 4;
-    const double *A = t.leaf_frag + g.slot_aoff[sl];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int idx = threadIdx.x + q * 256;
-      double v = 0.0;
-      if (idx < CH) {
-        const int i = idx / 256, j = (idx / 64) & 3, ln = idx & 63;
-        const int mt = i < MTG ? mt0 + i : mass_mt;
-        if (mt < MT && (i < MTG || extra_mass)) v = A[((size_t)mt * KS + ks0 + j) * 64 + ln];
-      }
-      reg[q] = v;
-    }
-  };
-  auto stage_store = [&](int buf, const double *reg) {
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int idx = threadIdx.x + q * 256;
-      if (idx < CH) sA[buf][idx] = reg[q];
-    }
-  };
-
+  const int *slot_type = g.slot_type, *slot_src = g.slot_src + wave * 16 + col, *slot_aoff = g.slot_aoff;
+  const double *leaf_frag = t.leaf_frag;
+  using Stage = LeafStage<PER>;
   dbl4 acc[NTS];
 #pragma unroll
   for (int m = 0; m < NTS; ++m) acc[m] = dbl4{0, 0, 0, 0};
-  double reg[PER];
+  Stage reg;
+  dbl4 bn = dbl4{0, 0, 0, 0};
   int sl = s0, ks0 = 0, buf = 0;
-  if (sl < s1) stage_load(sl, 0, reg);
+  if (sl < s1) {
+    reg = leaf_stage_load<MTG, PER>(leaf_frag, slot_type, slot_aoff, sl, 0, P, K2, mt0, MT, mass_mt, extra_mass);
+    bn = leaf_b_load(slot_type, slot_src, fr, Lr, Mr, sl, 0, P, K2, kq, inv_h2);
+  }
   while (sl < s1) {
-    const int type = g.slot_type[sl], src = g.slot_src[sl * LEAF_TILE + wave * 16 + col];
-    const int K = type == 0 ? P : K2, KS = K / 4;
-    stage_store(buf, reg);
+    const int KS = (slot_type[sl] == 0 ? P : K2) / 4;
+    const dbl4 bv = bn;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + q * 256;
+      if (idx < CH) sA[buf][idx] = reg.v[q];
+    }
     __syncthreads();
     // prefetch the next chunk (this slot's next 4 k-steps, or the next slot's first)
     int nsl = sl, nks = ks0 + 4;
     if (nks >= KS) { ++nsl; nks = 0; }
-    if (nsl < s1) stage_load(nsl, nks, reg);
-    const double *bp = type == 0 ? fr + (size_t)(src >= 0 ? src : 0) * P
-                                 : (type == 1 ? Lr : Mr) + (size_t)(src >= 0 ? src : 0) * K2;
-    const double sc = src < 0 ? 0.0 : (type == 0 ? 1.0 : inv_h2);
-    double bv[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) bv[j] = sc * bp[kq * KS + ks0 + j];
+    if (nsl < s1) {
+      reg = leaf_stage_load<MTG, PER>(leaf_frag, slot_type, slot_aoff, nsl, nks, P, K2, mt0, MT, mass_mt,
+                                      extra_mass);
+      bn = leaf_b_load(slot_type, slot_src, fr, Lr, Mr, nsl, nks, P, K2, kq, inv_h2);
+    }
     const double *S = sA[buf];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -367,10 +419,13 @@ void launch_p2m(const DevTables &t, const DevTree &g, const double *f, int nrhs,
   else if (t.KP == 32) hipLaunchKernelGGL(p2m_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, f, M);
   else hipLaunchKernelGGL(p2m_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, f, M);
 }
-void launch_m2m(const DevTables &t, const DevTree &g, int level, int box0, int box1, int nrhs, double *M,
+void launch_m2m(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *M,
                 hipStream_t s) {
-  (void)level;
-  if (box1 > box0) hipLaunchKernelGGL(m2m_kernel, dim3(box1 - box0, nrhs), dim3(64), 0, s, t, g, box0, M);
+  if (nbox <= 0) return;
+  dim3 grid((nbox + 15) / 16, nrhs);
+  if (t.KP == 16) hipLaunchKernelGGL(m2m_mfma_kernel<16>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
+  else if (t.KP == 32) hipLaunchKernelGGL(m2m_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
+  else hipLaunchKernelGGL(m2m_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
 }
 void launch_m2l(const DevTables &t, const DevTree &g, int nrhs, const double *M, double *L, hipStream_t s) {
   dim3 grid((g.n_boxes + 3) / 4, nrhs);
@@ -379,10 +434,19 @@ void launch_m2l(const DevTables &t, const DevTree &g, int nrhs, const double *M,
   else hipLaunchKernelGGL(m2l_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, M, L);
 }
 void launch_p2l(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *L, hipStream_t s) {
-  if (g.n_x_boxes > 0) hipLaunchKernelGGL(p2l_kernel, dim3(g.n_x_boxes, nrhs), dim3(64), 0, s, t, g, f, L);
+  if (g.n_xtiles <= 0) return;
+  dim3 grid((g.n_xtiles + 3) / 4, nrhs);
+  if (t.KP == 16) hipLaunchKernelGGL(p2l_mfma_kernel<16>, grid, dim3(256), 0, s, t, g, f, L);
+  else if (t.KP == 32) hipLaunchKernelGGL(p2l_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, f, L);
+  else hipLaunchKernelGGL(p2l_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, f, L);
 }
-void launch_l2l(const DevTables &t, const DevTree &g, int box0, int box1, int nrhs, double *L, hipStream_t s) {
-  if (box1 > box0) hipLaunchKernelGGL(l2l_kernel, dim3(box1 - box0, nrhs), dim3(64), 0, s, t, g, box0, L);
+void launch_l2l(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *L,
+                hipStream_t s) {
+  if (nbox <= 0) return;
+  dim3 grid((nbox + 15) / 16, nrhs, 4);
+  if (t.KP == 16) hipLaunchKernelGGL(l2l_mfma_kernel<16>, grid, dim3(256), 0, s, t, g, boxes, nbox, L);
+  else if (t.KP == 32) hipLaunchKernelGGL(l2l_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, boxes, nbox, L);
+  else hipLaunchKernelGGL(l2l_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, boxes, nbox, L);
 }
 void launch_leaf(const DevTables &t, const DevTree &g, const double *f, int nrhs, const double *M,
                  const double *L, double *V, double *G, hipStream_t s) {

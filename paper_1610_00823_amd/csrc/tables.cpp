@@ -530,6 +530,45 @@ void build_p2m_frag(const Tables &T, std::vector<double> &out) {
   append_frag(out, 2 * T.KP / 16, T.P, [&](int i, int k) { return T.p2m[(size_t)i * T.P + k]; });
 }
 
+// Real form of a complex coefficient map on interleaved (Re, Im) vectors.
+static double cplx_entry(double orr, double oi, int po, int pi) {
+  return po == pi ? orr : (po == 0 ? -oi : oi);
+}
+
+void build_m2m_frag(const Tables &T, std::vector<double> &out) {
+  const int R = 2 * T.KP, nt = T.nt;
+  out.clear();
+  for (int c = 0; c < 4; ++c)
+    append_frag(out, R / 16, R, [&](int o, int i) {
+      const int l = o / 2, kk = i / 2;
+      if (l >= nt || kk >= nt) return 0.0;
+      const double *op = &T.m2m[(((size_t)c * nt + l) * nt + kk) * 2];
+      return cplx_entry(op[0], op[1], o & 1, i & 1);
+    });
+}
+
+void build_l2l_frag(const Tables &T, std::vector<double> &out) {
+  const int R = 2 * T.KP, nt = T.nt;
+  out.clear();
+  for (int c = 0; c < 4; ++c)
+    append_frag(out, R / 16, R, [&](int o, int i) {
+      const int m = o / 2, l = i / 2;
+      if (m >= nt || l >= nt) return 0.0;
+      const double *op = &T.l2l[(((size_t)c * nt + m) * nt + l) * 2];
+      return cplx_entry(op[0], op[1], o & 1, i & 1);
+    });
+}
+
+void build_p2l_frag(const Tables &T, std::vector<double> &out) {
+  const int R = 2 * T.KP, KP = T.KP, P = T.P;
+  out.clear();
+  for (int c = 0; c < NCFG_X; ++c)
+    append_frag(out, (R + 16) / 16, P, [&](int o, int j) {
+      if (o < R) return T.p2l[((size_t)c * 2 * KP + (o & 1) * KP + o / 2) * P + j];
+      return o == R ? 4.0 * T.wq[j] : 0.0;
+    });
+}
+
 uint64_t tables_checksum(const Tables &T) {
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](const std::vector<double> &v) {

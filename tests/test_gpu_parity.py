@@ -134,3 +134,28 @@ def test_adaptive_gaussians_sampled_targets(ctx8):
     ey = np.abs(G[0][sel, 1] - Gyo).max() / np.abs(G[0][:, 1]).max()
     print(f"sampled {len(sel)} leaves: E(V)={ev:.2e} E(dV/dx1)={ex:.2e} E(dV/dx2)={ey:.2e}")
     assert ev < TOL and ex < TOL and ey < TOL
+
+
+def test_graph_replays_match_eager(ctx8):
+    # The evaluation is captured once into a hipGraph and replayed; each replay,
+    # with unrelated eager torch work and synchronisations in between and new
+    # data in the same buffers, must equal the eager (one launch per kernel) result.
+    torch = _torch()
+    t = I.point_refined_tree([[0.3, 0.2], [-0.26, -0.4]], [5, 4])
+    tr = B.Tree.from_inputs(ctx8, t)
+    rng = np.random.default_rng(21)
+    f = torch.from_numpy(rng.standard_normal((1, t.n_leaves, 8, 8))).cuda()
+    V = torch.empty_like(f)
+    G = torch.empty((1, t.n_leaves, 2, 8, 8), dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        f.copy_(torch.from_numpy(rng.standard_normal((1, t.n_leaves, 8, 8))))
+        ctx8.profile(True)                      # eager: one launch per kernel
+        Ve, Ge = B.volume_eval_grad(ctx8, tr, f)
+        torch.cuda.synchronize()
+        ctx8.profile(False)
+        ctx8.profile_read()
+        junk = torch.randn(1 << 20, device="cuda").sum()   # unrelated eager work
+        B.volume_eval_grad(ctx8, tr, f, V, G)   # captured on the first pass, replayed after
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        assert torch.equal(V, Ve) and torch.equal(G, Ge), f"replay {rep} differs"
