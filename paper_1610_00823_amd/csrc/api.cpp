@@ -165,13 +165,15 @@ int bx_build_tables(bx_ctx *ctx, double quad_tol, const char *cache_dir) {
       (rc = upload(ctx->dev, T.logd, &d.logd, s)) || (rc = upload(ctx->dev, T.l2t, &d.l2t, s)) ||
       (rc = upload(ctx->dev, T.m2t, &d.m2t, s)) || (rc = upload(ctx->dev, T.p2l, &d.p2l, s)))
     return rc;
-  std::vector<double> lf, pf, mf, llf, xf;
-  build_leaf_frag(T, lf);
+  std::vector<double> lf, lm, pf, mf, llf, xf;
+  build_leaf_frag(T, lf, lm);
   build_p2m_frag(T, pf);
   build_m2m_frag(T, mf);
   build_l2l_frag(T, llf);
   build_p2l_frag(T, xf);
-  if ((rc = upload(ctx->dev, lf, &d.leaf_frag, s)) || (rc = upload(ctx->dev, pf, &d.p2m_frag, s)) ||
+  d.leaf_kmax = leaf_frag_layout(T.n, T.p).KMAX;
+  if ((rc = upload(ctx->dev, lf, &d.leaf_frag, s)) || (rc = upload(ctx->dev, lm, &d.leaf_mass, s)) ||
+      (rc = upload(ctx->dev, pf, &d.p2m_frag, s)) ||
       (rc = upload(ctx->dev, mf, &d.m2m_frag, s)) || (rc = upload(ctx->dev, llf, &d.l2l_frag, s)) ||
       (rc = upload(ctx->dev, xf, &d.p2l_frag, s)))
     return rc;
@@ -220,7 +222,8 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
   for (int i = 0; i < H.n_leaves; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sig[a] < sig[b]; });
   int ntiles = (H.n_leaves + TL - 1) / TL;
-  std::vector<int> tile_tgt((size_t)ntiles * TL, -1), tile_ptr(ntiles + 1, 0), slot_aoff, slot_type, slot_src;
+  std::vector<int> tile_tgt((size_t)ntiles * TL, -1), tile_ptr(ntiles + 1, 0), slot_aoff, slot_type, slot_src,
+      slot_op;
   for (int tt = 0; tt < ntiles; ++tt) {
     uint64_t uni = 0;
     for (int k = 0; k < TL && tt * TL + k < H.n_leaves; ++k) {
@@ -232,6 +235,7 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       if (!(uni >> c & 1)) continue;
       slot_aoff.push_back((int)(FL.near0 + c * FL.near_step));
       slot_type.push_back(0);
+      slot_op.push_back(c);
       for (int k = 0; k < TL; ++k) {
         int leaf = tile_tgt[(size_t)tt * TL + k], src = -1;
         if (leaf >= 0)
@@ -242,6 +246,7 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
     }
     slot_aoff.push_back((int)FL.l2t);
     slot_type.push_back(1);
+    slot_op.push_back(NCFG_U);
     for (int k = 0; k < TL; ++k) {
       int leaf = tile_tgt[(size_t)tt * TL + k];
       slot_src.push_back(leaf >= 0 ? H.box_of_leaf[leaf] : -1);
@@ -250,6 +255,7 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       if (!(uni >> (NCFG_U + c) & 1)) continue;
       slot_aoff.push_back((int)(FL.w0 + c * FL.w_step));
       slot_type.push_back(2);
+      slot_op.push_back(NCFG_U + 1 + c);
       for (int k = 0; k < TL; ++k) {
         int leaf = tile_tgt[(size_t)tt * TL + k], src = -1;
         if (leaf >= 0)
@@ -321,6 +327,7 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       (rc = upload(t->dev, ib, &t->int_boxes, s)) ||
       (rc = upload(t->dev, tile_tgt, &g.tile_tgt, s)) || (rc = upload(t->dev, tile_ptr, &g.tile_ptr, s)) ||
       (rc = upload(t->dev, slot_aoff, &g.slot_aoff, s)) || (rc = upload(t->dev, slot_type, &g.slot_type, s)) ||
+      (rc = upload(t->dev, slot_op, &g.slot_op, s)) ||
       (rc = upload(t->dev, slot_src, &g.slot_src, s))) {
     bx_tree_destroy(t);
     return rc;

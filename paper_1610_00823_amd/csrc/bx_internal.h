@@ -46,13 +46,17 @@ struct Tables {
 int build_tables(Tables &T, int n, int p, double tol, int nthreads);
 
 // Fragment-major A operands of the fused leaf GEMM: 33 near tables (K = P),
-// then L2T, then the 20 W operators (K = 2 KP), each MR rows.
+// then L2T, then the 20 W operators (K = 2 KP); 3P rows each (V, dV/dx1,
+// dV/dx2).  K is cut into chunks of KC = min(64, P) columns:
+// frag[((mt * NC + c) * KSC + ks) * 64 + lane] = A[mt*16 + lane%16][c*KC + (lane/16)*KSC + ks],
+// NC = K / KC, KSC = KC / 4.  The mass row of each operator (its weights for
+// the log h term) is kept apart: mass[op][k], op = near c, 33 = L2T, 34 + W c.
 struct LeafFragLayout {
-  int MT, KSU, KSE;          // row tiles, k-steps of near slots, k-steps of expansion slots
+  int MTR, KC, KMAX;         // row tiles, chunk width, mass-vector stride
   int64_t near0, near_step, l2t, w0, w_step, total;
 };
 LeafFragLayout leaf_frag_layout(int n, int p);
-void build_leaf_frag(const Tables &T, std::vector<double> &out);
+void build_leaf_frag(const Tables &T, std::vector<double> &out, std::vector<double> &mass);
 void build_p2m_frag(const Tables &T, std::vector<double> &out);
 // M2M 4 x [2KP][2KP], L2L 4 x [2KP][2KP] on interleaved coefficients, and the
 // 20 P2L operators [2KP + mass row, padded to 16][P], fragment-major.

@@ -13,6 +13,8 @@ struct DevTables {
   // frag[((op * MT + mt) * KS + ks) * 64 + lane] = A[mt*16 + lane%16][(lane/16) * KS + ks],
   // K = 4 KS; the k index is split so that each lane's B operand is contiguous.
   const double *leaf_frag, *p2m_frag;
+  const double *leaf_mass;   // [54][KMAX] mass-row weights of the leaf operators
+  int leaf_kmax;
   // M2M 4 x [2KP][2KP] and L2L 4 x [2KP][2KP] on interleaved coefficients, and
   // P2L per X configuration [2KP + mass row, padded][P], all fragment-major.
   const double *m2m_frag, *l2l_frag, *p2l_frag;
@@ -48,6 +50,7 @@ struct DevTree {
   const int *tile_tgt;     // [n_tiles][64], -1 = padding
   const int *tile_ptr;     // [n_tiles + 1] into slots
   const int *slot_aoff;    // [n_slots] offset of the A fragments in leaf_frag
+  const int *slot_op;      // [n_slots] operator index (near c, 33 = L2T, 34 + W c)
   const int *slot_type;    // [n_slots] 0: samples f of a source leaf (K = P); 1: local expansion
                            // of the target's box; 2: multipole of a source box (K = 2 KP)
   const int *slot_src;     // [n_slots][64] leaf or box index, -1 = none

@@ -265,14 +265,16 @@ __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, c
 //   near tables  (K = P,    B = f of the source leaf),
 //   L2T          (K = 2KP,  B = local expansion of the target / h^2),
 //   W list       (K = 2KP,  B = multipole of the source box / h^2),
-// rows V (P), dV/dx1 (P), dV/dx2 (P), mass (1).  Then
-//   V = h^2 acc_V + (h^2 log h / 2pi) acc_mass,  grad V = h acc_D,
+// rows V (P), dV/dx1 (P), dV/dx2 (P); with mass = sum over slots of the
+// operators' mass weights times B,
+//   V = h^2 acc_V + (h^2 log h / 2pi) mass,  grad V = h acc_D,
 // which carries the per-level scaling of the unit-box tables, the a_0 log h
 // of the W multipoles and the 1/h of the gradients (the tables hold the rest).
-// Block = 4 waves = 64 leaves (16 per wave); the A fragments of each chunk of
-// 4 k-steps are loaded once per block into LDS (double buffered, the next
-// chunk prefetched into registers while the current one is multiplied).
-// grid.y splits the rows into groups of MTG tiles.
+// Block = 4 waves = 64 leaves.  The slot's B columns (64 x KC) are staged in
+// LDS once per block (double buffered through registers, one barrier per
+// chunk); wave w owns row tiles w, w+4, w+8, ... of its row group and all four
+// 16-leaf column tiles, so each A fragment read from the operator table feeds
+// four MFMAs.  grid.y splits the rows into groups of 4*TPW tiles.
 constexpr int LEAF_TILE = 64;
 
 // logical block index that gives each XCD (blocks are dealt round-robin to
@@ -283,132 +285,127 @@ __device__ inline int xcd_block(int b, int nb_logical) {
   return l < nb_logical ? l : -1;
 }
 
-template <int PER>
-struct LeafStage {
-  double v[PER];
+template <int N>
+struct Regs {
+  double v[N];
 };
 
-// This thread's share of one chunk of A fragments (4 k-steps of every staged
-// row tile; tile i < MTG is row tile mt0 + i, tile MTG the mass row's tile).
-template <int MTG, int PER>
-__device__ __forceinline__ LeafStage<PER> leaf_stage_load(const double *__restrict__ leaf_frag,
-                                                          const int *__restrict__ slot_type,
-                                                          const int *__restrict__ slot_aoff, int sl, int ks0,
-                                                          int P, int K2, int mt0, int MT, int mass_mt,
-                                                          bool extra_mass) {
-  constexpr int CH = (MTG + 1) * 4 * 64;
-  const int KS = (slot_type[sl] == 0 ? P : K2) / 4;
-  const double *A = leaf_frag + slot_aoff[sl];
-  LeafStage<PER> st;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int idx = threadIdx.x + q * 256;
-    double v = 0.0;
-    if (idx < CH) {
-      const int i = idx / 256, j = (idx / 64) & 3, ln = idx & 63;
-      const int mt = i < MTG ? mt0 + i : mass_mt;
-      if (mt < MT && (i < MTG || extra_mass)) v = A[((size_t)mt * KS + ks0 + j) * 64 + ln];
-    }
-    st.v[q] = v;
-  }
-  return st;
-}
-
-// B operand of chunk (slot, ks0) for this lane: 4 consecutive k of its column
-// (slot_src already offset to the lane's column).
-__device__ __forceinline__ dbl4 leaf_b_load(const int *__restrict__ slot_type, const int *__restrict__ slot_src,
-                                            const double *fr, const double *Lr, const double *Mr, int sl, int ks0,
-                                            int P, int K2, int kq, double inv_h2) {
+// This thread's quarter (KC/4 values) of column scol of chunk c of slot sl
+// (slot_src already offset to the column).
+template <int KC>
+__device__ __forceinline__ Regs<KC / 4> leaf_chunk_load(const int *__restrict__ slot_type,
+                                                         const int *__restrict__ slot_src, const double *fr,
+                                                         const double *Lr, const double *Mr, int sl, int c, int P,
+                                                         int K2, int sq, double sinv_h2) {
+  constexpr int PERT = KC / 4;
   const int type = slot_type[sl], src = slot_src[sl * LEAF_TILE];
-  const int KS = (type == 0 ? P : K2) / 4;
   const double *bp = type == 0 ? fr + (size_t)(src >= 0 ? src : 0) * P
                                : (type == 1 ? Lr : Mr) + (size_t)(src >= 0 ? src : 0) * K2;
-  const double sc = src < 0 ? 0.0 : (type == 0 ? 1.0 : inv_h2);
-  const double *q = bp + kq * KS + ks0;
-  return dbl4{sc * q[0], sc * q[1], sc * q[2], sc * q[3]};
+  const double sc = src < 0 ? 0.0 : (type == 0 ? 1.0 : sinv_h2);
+  const double *q = bp + c * KC + sq * PERT;
+  Regs<PERT> r;
+#pragma unroll
+  for (int j = 0; j < PERT; ++j) r.v[j] = sc * q[j];
+  return r;
 }
 
-template <int MTG>
+template <int TPW, int KC>
 __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree g, const double *__restrict__ f,
                                                            const double *__restrict__ M,
                                                            const double *__restrict__ L, double *__restrict__ V,
-                                                           double *__restrict__ G, int mass_mt) {
-  constexpr int NTS = MTG + 1;                 // staged row tiles: the group plus a mass tile
-  constexpr int CH = NTS * 4 * 64;             // doubles per staged chunk
-  constexpr int PER = (CH + 255) / 256;        // doubles each thread stages
-  __shared__ double sA[2][CH];
+                                                           double *__restrict__ G) {
+  constexpr int KSC = KC / 4, PERT = KC / 4, SB = KC + 1;
+  __shared__ double sB[2][LEAF_TILE * SB];
+  __shared__ double sMass[LEAF_TILE];
   const int tile = xcd_block(blockIdx.x, g.n_tiles);
   if (tile < 0) return;                        // whole block: no barrier is skipped
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
-  const int rhs = blockIdx.z, mt0 = blockIdx.y * MTG, P = t.P, K2 = 2 * t.KP;
-  const int MT = t.MR / 16;
-  const int tgt = g.tile_tgt[tile * LEAF_TILE + wave * 16 + col];
-  const double h = tgt >= 0 ? box_h(g.width, g.leaf_level[tgt]) : 1.0, inv_h2 = 1.0 / (h * h);
-  const bool vrows = mt0 * 16 < P;
-  const bool extra_mass = vrows && (mass_mt < mt0 || mass_mt >= mt0 + MTG);
+  const int rhs = blockIdx.z, P = t.P, K2 = 2 * t.KP, MTR = 3 * P / 16;
+  const int mtg = blockIdx.y * 4 * TPW;        // first row tile of this group
   const int s0 = g.tile_ptr[tile], s1 = g.tile_ptr[tile + 1];
   const double *fr = f + (size_t)rhs * g.n_leaves * P;
   const double *Lr = L + (size_t)rhs * g.n_boxes * K2, *Mr = M + (size_t)rhs * g.n_boxes * K2;
-  const int *slot_type = g.slot_type, *slot_src = g.slot_src + wave * 16 + col, *slot_aoff = g.slot_aoff;
-  const double *leaf_frag = t.leaf_frag;
-  using Stage = LeafStage<PER>;
-  dbl4 acc[NTS];
+  const int *slot_type = g.slot_type, *slot_op = g.slot_op, *slot_aoff = g.slot_aoff;
+  const double *leaf_frag = t.leaf_frag, *leaf_mass = t.leaf_mass;
+  const int kmax = t.leaf_kmax;
+
+  // staging role: 4 threads per column, each a quarter (PERT values) of the chunk
+  const int scol = threadIdx.x >> 2, sq = threadIdx.x & 3;
+  const int stgt = g.tile_tgt[tile * LEAF_TILE + scol];
+  const double sinv_h2 = stgt >= 0 ? 1.0 / (box_h(g.width, g.leaf_level[stgt]) * box_h(g.width, g.leaf_level[stgt]))
+                                   : 0.0;
+  const int *slot_src = g.slot_src + scol;
+  dbl4 acc[TPW][4];
 #pragma unroll
-  for (int m = 0; m < NTS; ++m) acc[m] = dbl4{0, 0, 0, 0};
-  Stage reg;
-  dbl4 bn = dbl4{0, 0, 0, 0};
-  int sl = s0, ks0 = 0, buf = 0;
-  if (sl < s1) {
-    reg = leaf_stage_load<MTG, PER>(leaf_frag, slot_type, slot_aoff, sl, 0, P, K2, mt0, MT, mass_mt, extra_mass);
-    bn = leaf_b_load(slot_type, slot_src, fr, Lr, Mr, sl, 0, P, K2, kq, inv_h2);
-  }
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[i][nt] = dbl4{0, 0, 0, 0};
+  double mpart = 0.0;
+  Regs<PERT> rb;
+  int sl = s0, c = 0, buf = 0;
+  if (sl < s1) rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, sl, 0, P, K2, sq, sinv_h2);
   while (sl < s1) {
-    const int KS = (slot_type[sl] == 0 ? P : K2) / 4;
-    const dbl4 bv = bn;
+    const int K = slot_type[sl] == 0 ? P : K2, NC = K / KC;
+    {   // stage this chunk's B columns and add their mass weights
+      const double *mw = leaf_mass + (size_t)slot_op[sl] * kmax + c * KC + sq * PERT;
+      double *dst = &sB[buf][scol * SB + sq * PERT];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int idx = threadIdx.x + q * 256;
-      if (idx < CH) sA[buf][idx] = reg.v[q];
+      for (int j = 0; j < PERT; ++j) {
+        dst[j] = rb.v[j];
+        mpart = fma(mw[j], rb.v[j], mpart);
+      }
     }
     __syncthreads();
-    // prefetch the next chunk (this slot's next 4 k-steps, or the next slot's first)
-    int nsl = sl, nks = ks0 + 4;
-    if (nks >= KS) { ++nsl; nks = 0; }
-    if (nsl < s1) {
-      reg = leaf_stage_load<MTG, PER>(leaf_frag, slot_type, slot_aoff, nsl, nks, P, K2, mt0, MT, mass_mt,
-                                      extra_mass);
-      bn = leaf_b_load(slot_type, slot_src, fr, Lr, Mr, nsl, nks, P, K2, kq, inv_h2);
+    const double *A = leaf_frag + slot_aoff[sl] + (size_t)c * KSC * 64;
+    int nsl = sl, nc = c + 1;
+    if (nc >= NC) { ++nsl; nc = 0; }
+    if (nsl < s1)                                  // next chunk in flight during the MFMAs
+      rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, nsl, nc, P, K2, sq, sinv_h2);
+    const double *S = sB[buf];
+#pragma unroll 4
+    for (int ks = 0; ks < KSC; ++ks) {
+      double a[TPW];
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int mt = mtg + wave + 4 * i;
+        a[i] = mt < MTR ? A[((size_t)mt * NC * KSC + ks) * 64 + lane] : 0.0;
+      }
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const double b = S[(nt * 16 + col) * SB + kq * KSC + ks];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) acc[i][nt] = mfma4(a[i], b, acc[i][nt]);
+      }
     }
-    const double *S = sA[buf];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int m = 0; m < NTS; ++m)
-        if (m < MTG || extra_mass) acc[m] = mfma4(S[(m * 4 + j) * 64 + lane], bv[j], acc[m]);
     sl = nsl;
-    ks0 = nks;
+    c = nc;
     buf ^= 1;
   }
-  double mass = 0.0;
-  if (vrows) {
-    double mv = acc[MTG][0];
+  // mass of each column: sum over its 4 staging threads (adjacent lanes)
+  mpart += __shfl_xor(mpart, 1);
+  mpart += __shfl_xor(mpart, 2);
+  if (sq == 0) sMass[scol] = mpart;
+  __syncthreads();
 #pragma unroll
-    for (int m = 0; m < MTG; ++m)
-      if (mt0 + m == mass_mt) mv = acc[m][0];
-    mass = __shfl(mv, col);                              // row 0 of the mass tile lives in lanes 0..15
-  }
-  if (tgt < 0) return;
-  const double lg = h * h * log(h) * kInv2Pi * mass;
-  double *Vt = V + ((size_t)rhs * g.n_leaves + tgt) * P;
-  double *Gt = G + ((size_t)rhs * g.n_leaves + tgt) * 2 * P;
+  for (int nt = 0; nt < 4; ++nt) {
+    const int tgt = g.tile_tgt[tile * LEAF_TILE + nt * 16 + col];
+    if (tgt < 0) continue;
+    const double h = box_h(g.width, g.leaf_level[tgt]);
+    const double lg = h * h * log(h) * kInv2Pi * sMass[nt * 16 + col];
+    double *Vt = V + ((size_t)rhs * g.n_leaves + tgt) * P;
+    double *Gt = G + ((size_t)rhs * g.n_leaves + tgt) * 2 * P;
 #pragma unroll
-  for (int m = 0; m < MTG; ++m)
+    for (int i = 0; i < TPW; ++i) {
+      const int mt = mtg + wave + 4 * i;
+      if (mt >= MTR) continue;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = (mt0 + m) * 16 + 4 * r + kq;
-      if (row < P) Vt[row] = h * h * acc[m][r] + lg;
-      else if (row < 3 * P) Gt[row - P] = h * acc[m][r];
+      for (int r = 0; r < 4; ++r) {
+        const int row = mt * 16 + 4 * r + kq;
+        if (row < P) Vt[row] = h * h * acc[i][nt][r] + lg;
+        else Gt[row - P] = h * acc[i][nt][r];
+      }
     }
+  }
 }
 
 }  // namespace
@@ -450,14 +447,13 @@ void launch_l2l(const DevTables &t, const DevTree &g, const int *boxes, int nbox
 }
 void launch_leaf(const DevTables &t, const DevTree &g, const double *f, int nrhs, const double *M,
                  const double *L, double *V, double *G, hipStream_t s) {
-  const int mass_mt = 3 * t.P / 16;
   const int bx = (g.n_tiles + 7) / 8 * 8;     // padded to a multiple of the 8 XCDs
-  if (t.n == 4) {
-    hipLaunchKernelGGL(leaf_mfma_kernel<4>, dim3(bx, 1, nrhs), dim3(256), 0, s, t, g, f, M, L, V, G, mass_mt);
-  } else if (t.n == 8) {
-    hipLaunchKernelGGL(leaf_mfma_kernel<13>, dim3(bx, 1, nrhs), dim3(256), 0, s, t, g, f, M, L, V, G, mass_mt);
-  } else {
-    hipLaunchKernelGGL(leaf_mfma_kernel<16>, dim3(bx, 3, nrhs), dim3(256), 0, s, t, g, f, M, L, V, G, mass_mt);
+  if (t.n == 4) {         // 3 row tiles, K chunks of 16
+    hipLaunchKernelGGL((leaf_mfma_kernel<1, 16>), dim3(bx, 1, nrhs), dim3(256), 0, s, t, g, f, M, L, V, G);
+  } else if (t.n == 8) {  // 12 row tiles: 3 per wave
+    hipLaunchKernelGGL((leaf_mfma_kernel<3, 64>), dim3(bx, 1, nrhs), dim3(256), 0, s, t, g, f, M, L, V, G);
+  } else {                // 48 row tiles: 3 groups of 16, 4 per wave
+    hipLaunchKernelGGL((leaf_mfma_kernel<4, 64>), dim3(bx, 3, nrhs), dim3(256), 0, s, t, g, f, M, L, V, G);
   }
 }
 

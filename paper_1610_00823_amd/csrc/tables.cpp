@@ -470,14 +470,14 @@ int build_tables(Tables &T, int n, int p, double tol, int nthreads) {
 
 LeafFragLayout leaf_frag_layout(int n, int p) {
   LeafFragLayout L;
-  const int P = n * n, KP = (p + 1 + 15) / 16 * 16, MR = (3 * P + 1 + 15) / 16 * 16;
-  L.MT = MR / 16;
-  L.KSU = P / 4;
-  L.KSE = 2 * KP / 4;
+  const int P = n * n, KP = (p + 1 + 15) / 16 * 16;
+  L.MTR = 3 * P / 16;
+  L.KC = std::min(64, P);
+  L.KMAX = std::max(P, 2 * KP);
   L.near0 = 0;
-  L.near_step = (int64_t)L.MT * L.KSU * 64;
+  L.near_step = (int64_t)L.MTR * P * 16;           // MTR tiles x K/4 steps x 64 lanes
   L.l2t = L.near0 + NCFG_U * L.near_step;
-  L.w_step = (int64_t)L.MT * L.KSE * 64;
+  L.w_step = (int64_t)L.MTR * 2 * KP * 16;
   L.w0 = L.l2t + L.w_step;
   L.total = L.w0 + NCFG_W * L.w_step;
   return L;
@@ -485,43 +485,48 @@ LeafFragLayout leaf_frag_layout(int n, int p) {
 
 namespace {
 // Append the MFMA A fragments of a rows x K matrix (element (i, k) = a(i, k)),
-// row tiles of 16 and k split as k = (lane / 16) * KS + ks.
+// row tiles of 16, K in chunks of KC, within a chunk k = (lane / 16) * KSC + ks.
+template <class F>
+void append_frag_chunked(std::vector<double> &out, int MT, int K, int KC, F a) {
+  const int NC = K / KC, KSC = KC / 4;
+  for (int mt = 0; mt < MT; ++mt)
+    for (int c = 0; c < NC; ++c)
+      for (int ks = 0; ks < KSC; ++ks)
+        for (int lane = 0; lane < 64; ++lane) out.push_back(a(mt * 16 + (lane & 15), c * KC + (lane >> 4) * KSC + ks));
+}
 template <class F>
 void append_frag(std::vector<double> &out, int MT, int K, F a) {
-  const int KS = K / 4;
-  for (int mt = 0; mt < MT; ++mt)
-    for (int ks = 0; ks < KS; ++ks)
-      for (int lane = 0; lane < 64; ++lane) out.push_back(a(mt * 16 + (lane & 15), (lane >> 4) * KS + ks));
+  append_frag_chunked(out, MT, K, K, a);
 }
 }  // namespace
 
-void build_leaf_frag(const Tables &T, std::vector<double> &out) {
+void build_leaf_frag(const Tables &T, std::vector<double> &out, std::vector<double> &mass) {
   const LeafFragLayout L = leaf_frag_layout(T.n, T.p);
-  const int P = T.P, KP = T.KP, MR = T.MR;
+  const int P = T.P, KP = T.KP, MR = T.MR, K2 = 2 * KP;
   out.clear();
   out.reserve(L.total);
+  mass.assign((size_t)(NCFG_U + 1 + NCFG_W) * L.KMAX, 0.0);
   for (int c = 0; c < NCFG_U; ++c) {
     const double *A = &T.near_[(size_t)c * MR * P];
-    append_frag(out, L.MT, P, [&](int i, int k) { return A[(size_t)i * P + k]; });
+    append_frag_chunked(out, L.MTR, P, L.KC, [&](int i, int k) { return A[(size_t)i * P + k]; });
+    for (int k = 0; k < P; ++k) mass[(size_t)c * L.KMAX + k] = A[(size_t)3 * P * P + k];
   }
   // expansion columns are stored interleaved (Re b_m, Im b_m) as in device memory
-  append_frag(out, L.MT, 2 * KP, [&](int i, int k) {
-    if (i >= 3 * P) return 0.0;
-    return T.l2t[(size_t)i * 2 * KP + (k & 1) * KP + k / 2];
+  append_frag_chunked(out, L.MTR, K2, L.KC, [&](int i, int k) {
+    return T.l2t[(size_t)i * K2 + (k & 1) * KP + k / 2];
   });
   // W: V rows carry log|e| - log 2 in the a_0 column (log(h/2) = log h - log 2, the
-  // log h part comes through the mass row), gradient rows are doubled (1/(h/2)).
+  // log h part comes through the mass weight on a_0), gradient rows are doubled (1/(h/2)).
   const double log2_2pi = std::log(2.0) / (2 * 3.14159265358979323846);
   for (int c = 0; c < NCFG_W; ++c) {
-    const double *A = &T.m2t[(size_t)c * 3 * P * 2 * KP];
-    append_frag(out, L.MT, 2 * KP, [&](int i, int k) {
-      if (i == 3 * P) return k == 0 ? 1.0 : 0.0;
-      if (i > 3 * P) return 0.0;
-      double v = A[(size_t)i * 2 * KP + (k & 1) * KP + k / 2];
+    const double *A = &T.m2t[(size_t)c * 3 * P * K2];
+    append_frag_chunked(out, L.MTR, K2, L.KC, [&](int i, int k) {
+      double v = A[(size_t)i * K2 + (k & 1) * KP + k / 2];
       if (i < P && k == 0) v -= log2_2pi;
       if (i >= P) v *= 2.0;
       return v;
     });
+    mass[(size_t)(NCFG_U + 1 + c) * L.KMAX + 0] = 1.0;
   }
 }
 
