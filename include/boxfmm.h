@@ -134,6 +134,7 @@ enum {
   BX_Q_NEAR_TILES = 11,      /* 16-target tiles of the near kernel */
   BX_Q_NEAR_SLOTS = 12,      /* (tile, configuration) slots of the near kernel */
   BX_Q_UPLOAD_MS = 13,       /* host time of the last bx_tree_upload, milliseconds */
+  BX_Q_SPLIT_PRODUCTS = 14,  /* split contexts: mean BF16 slice products per near table, over leaves */
   /* algorithmic FP64 flops of one evaluation phase, one RHS: add the phase index */
   BX_Q_PHASE_FLOPS = 20,
   /* algorithmic bytes of one evaluation phase (each operand read and each result
@@ -176,6 +177,16 @@ int bx_tree_list(const bx_tree *tree, int kind, int64_t *out, int64_t cap, int64
  * KP = p+1 rounded up to 16.  With out == NULL only *count is written.
  */
 int bx_table_copy(const bx_ctx *ctx, int which, double *out, int64_t cap, int64_t *count);
+
+/*
+ * Split contexts: tolerance of the BF16 slicing of the near tables.  The slice
+ * count of each level is the smallest with a truncation bound below
+ * tol * ||f||_inf * W^2 for V and tol * ||f||_inf * W for grad V (W = root
+ * width; V rows and gradient rows have their own counts), at most 6 slices
+ * (48 bits).  Takes effect for trees uploaded after the call; default 1e-11.
+ * Errors: BX_E_ARG.
+ */
+int bx_split_tolerance(bx_ctx *ctx, double tol);
 
 /*
  * Per-phase timing with HIP events recorded on the evaluation stream.

@@ -19,12 +19,14 @@ BX_E_ARG, BX_E_NOT_BALANCED, BX_E_INVALID_TREE, BX_E_UNSUPPORTED, BX_E_HIP, BX_E
     -1, -2, -3, -4, -5, -6, -7)
 BX_FP64, BX_SPLIT_BF16, BX_HOST_ONLY = 0, 1, 0x100
 Q = dict(n_leaves=0, n_boxes=1, n_levels=2, nodes=3, order=4, near_pairs=5, v_pairs=6, w_pairs=7,
-         x_pairs=8, near_flops=9, far_flops=10, near_tiles=11, near_slots=12, upload_ms=13)
+         x_pairs=8, near_flops=9, far_flops=10, near_tiles=11, near_slots=12, upload_ms=13,
+         split_products=14)
 TABLES = dict(near=0, p2m=1, m2m=2, l2l=3, m2l_core=4, m2l_src_pow=5, m2l_tgt_pow=6, logd=7, l2t=8,
               m2t=9, p2l=10, weights=11)
 PHASES = ["p2m", "m2m", "m2l", "p2l", "l2l", "leaf"]
 SYMBOLS = ["bx_create", "bx_build_tables", "bx_tree_upload", "bx_volume_eval_grad", "bx_volume_eval",
-           "bx_volume_grad", "bx_query", "bx_tree_list", "bx_table_copy", "bx_profile", "bx_profile_read",
+           "bx_volume_grad", "bx_query", "bx_tree_list", "bx_table_copy", "bx_split_tolerance", "bx_profile",
+           "bx_profile_read",
            "bx_tree_destroy", "bx_destroy", "bx_last_error"]
 
 _lib = None
@@ -59,6 +61,7 @@ def lib():
         L.bx_query.argtypes = [vp, vp, i32, ctypes.POINTER(dp)]
         L.bx_tree_list.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
         L.bx_table_copy.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
+        L.bx_split_tolerance.argtypes = [vp, dp]
         L.bx_profile.argtypes = [vp, i32]
         L.bx_profile_read.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(i32)]
         L.bx_tree_destroy.argtypes = [vp]
@@ -105,6 +108,9 @@ class Context:
         out = np.zeros(cnt.value)
         _check(lib().bx_table_copy(self._h, TABLES[name], out.ctypes.data, cnt.value, ctypes.byref(cnt)))
         return out
+
+    def split_tolerance(self, tol: float):
+        _check(lib().bx_split_tolerance(self._h, float(tol)))
 
     def profile(self, enable: bool = True):
         _check(lib().bx_profile(self._h, int(bool(enable))))

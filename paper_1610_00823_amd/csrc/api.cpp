@@ -14,6 +14,8 @@
 struct bx_ctx {
   int n = 0, p = 0, device = 0;
   uint32_t flags = 0;
+  double split_tol = 1e-11;              // slice-truncation tolerance of the split near tables
+  bx::SplitTables split;
   bool ready = false;
   bool profiling = false;
   std::vector<hipEvent_t> ev;            // recorded event pairs, phase-tagged
@@ -42,6 +44,7 @@ struct bx_tree {
   std::vector<void *> dev;
   bx::DevTree dg{};
   double *M = nullptr, *L = nullptr;   // expansions, grown with n_rhs
+  double *fscale = nullptr;            // split contexts: per-leaf sample scales [n_rhs][N_L]
   int exp_rhs = 0;
   double upload_ms = 0.0;
   int64_t n_slots = 0;
@@ -116,6 +119,8 @@ int bx_create(bx_ctx **out, int n_nodes, int p_exp, uint32_t flags) {
   if (p_exp < 8 || p_exp > 47) return fail(BX_E_UNSUPPORTED, "bx_create: p must be in 8..47");
   uint32_t prec = flags & ~(uint32_t)BX_HOST_ONLY;
   if (prec != BX_FP64 && prec != BX_SPLIT_BF16) return fail(BX_E_UNSUPPORTED, "bx_create: unknown flags");
+  if (prec == BX_SPLIT_BF16 && n_nodes == 4)
+    return fail(BX_E_UNSUPPORTED, "bx_create: split near tables need n = 8 or 16");
   int dev = 0;
   if (!(flags & BX_HOST_ONLY)) {
     hipError_t e = hipGetDevice(&dev);
@@ -148,6 +153,7 @@ int bx_build_tables(bx_ctx *ctx, double quad_tol, const char *cache_dir) {
     if (rc) return fail(rc, "bx_build_tables: table construction failed");
     if (!path.empty()) save_tables(T, path);   // a failed cache write is not an error
   }
+  if (ctx->flags & BX_SPLIT_BF16) build_split_tables(T, ctx->split);
   if (ctx->flags & BX_HOST_ONLY) {
     ctx->ready = true;
     return BX_OK;
@@ -177,6 +183,10 @@ int bx_build_tables(bx_ctx *ctx, double quad_tol, const char *cache_dir) {
       (rc = upload(ctx->dev, mf, &d.m2m_frag, s)) || (rc = upload(ctx->dev, llf, &d.l2l_frag, s)) ||
       (rc = upload(ctx->dev, xf, &d.p2l_frag, s)))
     return rc;
+  d.near_bf16 = nullptr;
+  d.split_scale_v = ctx->split.scale_v;
+  d.split_scale_d = ctx->split.scale_d;
+  if ((ctx->flags & BX_SPLIT_BF16) && (rc = upload(ctx->dev, ctx->split.a, &d.near_bf16, s))) return rc;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "bx_build_tables: upload");
   ctx->ready = true;
@@ -220,16 +230,35 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
   }
   std::vector<int> order(H.n_leaves);
   for (int i = 0; i < H.n_leaves; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sig[a] < sig[b]; });
-  int ntiles = (H.n_leaves + TL - 1) / TL;
+  // split contexts: tiles hold one level (the slice count depends on it)
+  const bool split = (ctx->flags & BX_SPLIT_BF16) != 0;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (split && leaf_level[a] != leaf_level[b]) return leaf_level[a] > leaf_level[b];
+    return sig[a] < sig[b];
+  });
+  std::vector<int> tile_first;   // tile -> index in order of its first leaf
+  for (int i = 0; i < H.n_leaves;) {
+    tile_first.push_back(i);
+    int j = i + 1;
+    while (j < H.n_leaves && j - i < TL && (!split || leaf_level[order[j]] == leaf_level[order[i]])) ++j;
+    i = j;
+  }
+  int ntiles = (int)tile_first.size();
+  tile_first.push_back(H.n_leaves);
+  std::vector<int> tile_nsl(ntiles, 0);
   std::vector<int> tile_tgt((size_t)ntiles * TL, -1), tile_ptr(ntiles + 1, 0), slot_aoff, slot_type, slot_src,
       slot_op;
   for (int tt = 0; tt < ntiles; ++tt) {
     uint64_t uni = 0;
-    for (int k = 0; k < TL && tt * TL + k < H.n_leaves; ++k) {
-      int leaf = order[tt * TL + k];
+    for (int k = 0; k < TL && tile_first[tt] + k < tile_first[tt + 1]; ++k) {
+      int leaf = order[tile_first[tt] + k];
       tile_tgt[(size_t)tt * TL + k] = leaf;
       uni |= sig[leaf];
+    }
+    if (split) {   // slices of the V rows (low byte) and of the gradient rows (next byte)
+      const int lv = leaf_level[order[tile_first[tt]]];
+      tile_nsl[tt] = split_slices(ctx->split, lv, ctx->split_tol, false) |
+                     split_slices(ctx->split, lv, ctx->split_tol, true) << 8;
     }
     for (int c = 0; c < NCFG_U; ++c) {
       if (!(uni >> c & 1)) continue;
@@ -327,7 +356,7 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       (rc = upload(t->dev, ib, &t->int_boxes, s)) ||
       (rc = upload(t->dev, tile_tgt, &g.tile_tgt, s)) || (rc = upload(t->dev, tile_ptr, &g.tile_ptr, s)) ||
       (rc = upload(t->dev, slot_aoff, &g.slot_aoff, s)) || (rc = upload(t->dev, slot_type, &g.slot_type, s)) ||
-      (rc = upload(t->dev, slot_op, &g.slot_op, s)) ||
+      (rc = upload(t->dev, slot_op, &g.slot_op, s)) || (rc = upload(t->dev, tile_nsl, &g.tile_nsl, s)) ||
       (rc = upload(t->dev, slot_src, &g.slot_src, s))) {
     bx_tree_destroy(t);
     return rc;
@@ -358,8 +387,11 @@ static int ensure_expansions(bx_tree *t, int nrhs) {
   t->M = t->L = nullptr;
   t->exp_rhs = 0;
   size_t bytes = (size_t)nrhs * t->H.n_boxes * t->ctx->T.KP * 2 * sizeof(double);
+  if (t->fscale) (void)hipFree(t->fscale);
+  t->fscale = nullptr;
   hipError_t e = hipMalloc((void **)&t->M, bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&t->L, bytes);
+  if (e == hipSuccess) e = hipMalloc((void **)&t->fscale, (size_t)nrhs * t->H.n_leaves * sizeof(double));
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(BX_E_OOM, "expansion buffers") : hip_fail(e, "hipMalloc");
   t->exp_rhs = nrhs;
   return BX_OK;
@@ -400,7 +432,8 @@ static int enqueue_eval(bx_ctx *ctx, bx_tree *t, const double *f, int nrhs, doub
   for (int l = 0; l + 1 < H.n_levels; ++l)
     launch_l2l(d, g, t->int_boxes + t->int_start[l], t->int_start[l + 1] - t->int_start[l], nrhs, t->L, s);
   if ((rc = mark(BX_PH_L2L, false)) || (rc = mark(BX_PH_LEAF, true))) return rc;
-  launch_leaf(d, g, f, nrhs, t->M, t->L, V, G, s);
+  if (ctx->flags & BX_SPLIT_BF16) launch_leaf_split(d, g, f, t->fscale, nrhs, t->M, t->L, V, G, s);
+  else launch_leaf(d, g, f, nrhs, t->M, t->L, V, G, s);
   if ((rc = mark(BX_PH_LEAF, false))) return rc;
   if (ctx->profiling) ctx->ev_evals++;
   hipError_t e = hipGetLastError();
@@ -481,6 +514,12 @@ int bx_volume_grad(bx_ctx *ctx, const bx_tree *tree, const double *f_dev, int n_
                    bx_stream_t stream) {
   if (!G_dev) return fail(BX_E_ARG, "bx_volume_grad: NULL output");
   return scratch_eval(ctx, tree, f_dev, n_rhs, nullptr, G_dev, false, stream);
+}
+
+int bx_split_tolerance(bx_ctx *ctx, double tol) {
+  if (!ctx || !(tol > 0.0) || tol >= 1.0) return fail(BX_E_ARG, "bx_split_tolerance: need 0 < tol < 1");
+  ctx->split_tol = tol;
+  return BX_OK;
 }
 
 int bx_profile(bx_ctx *ctx, int enable) {
@@ -568,6 +607,18 @@ int bx_query(const bx_ctx *ctx, const bx_tree *tree, int what, double *out) {
     case BX_Q_NEAR_TILES: *out = tree->dg.n_tiles; break;
     case BX_Q_NEAR_SLOTS: *out = (double)tree->n_slots; break;
     case BX_Q_UPLOAD_MS: *out = tree->upload_ms; break;
+    case BX_Q_SPLIT_PRODUCTS: {   // BF16 slice products per near (target, source) pair, averaged over pairs
+      if (!(ctx->flags & BX_SPLIT_BF16)) { *out = 0; break; }
+      double num = 0, den = 0;
+      for (int i = 0; i < H.n_leaves; ++i) {
+        int sv = split_slices(ctx->split, H.lvl[H.box_of_leaf[i]], ctx->split_tol, false);
+        int sd = split_slices(ctx->split, H.lvl[H.box_of_leaf[i]], ctx->split_tol, true);
+        num += (sv * (sv + 1) / 2.0 + 2.0 * sd * (sd + 1) / 2.0) / 3.0;   // V rows : gradient rows = 1 : 2
+        den += 1;
+      }
+      *out = den > 0 ? num / den : 0;
+      break;
+    }
     default: {
       double fl, by;
       if (what >= BX_Q_PHASE_FLOPS && what < BX_Q_PHASE_FLOPS + BX_N_PHASES) {
@@ -626,6 +677,7 @@ void bx_tree_destroy(bx_tree *tree) {
   for (void *p : tree->dev) (void)hipFree(p);
   if (tree->M) (void)hipFree(tree->M);
   if (tree->L) (void)hipFree(tree->L);
+  if (tree->fscale) (void)hipFree(tree->fscale);
   delete tree;
 }
 

@@ -57,6 +57,24 @@ struct LeafFragLayout {
 };
 LeafFragLayout leaf_frag_layout(int n, int p);
 void build_leaf_frag(const Tables &T, std::vector<double> &out, std::vector<double> &mass);
+
+// Split (BF16-slice) form of the near tables.  Each table row type (V rows,
+// gradient rows) shares one power-of-two scale 2^E; a value x is written as
+// sum_a s_a 2^(E - 8(a+1)) with integers |s_a| <= 256 taken by truncation; each
+// slice is stored with its scale (exact in BF16).  Fragments for
+// v_mfma_f32_16x16x32_bf16:
+// a[(((((c * SMAX + a) * MTR + mt) * NC + chunk) * 2 + step) * 64 + lane) * 8 + e]
+//   = slice a of A[mt*16 + lane%16][chunk*KC + step*32 + (lane/16)*8 + e] (bits of a BF16).
+constexpr int SPLIT_SMAX = 6;
+struct SplitTables {
+  std::vector<uint16_t> a;
+  double scale_v = 1.0, scale_d = 1.0;   // 2^E of the V rows and of the gradient rows
+  double bound_v = 0.0, bound_d = 0.0;   // max over rows of sum over configs and k of 2^E (error bound factor)
+};
+void build_split_tables(const Tables &T, SplitTables &S);
+// Slices needed at level l so that the slice truncation stays below tol times
+// ||f||_inf W^2 (V) and ||f||_inf W (gradient), W the root width.
+int split_slices(const SplitTables &S, int level, double tol, bool grad_rows);
 void build_p2m_frag(const Tables &T, std::vector<double> &out);
 // M2M 4 x [2KP][2KP], L2L 4 x [2KP][2KP] on interleaved coefficients, and the
 // 20 P2L operators [2KP + mass row, padded to 16][P], fragment-major.

@@ -15,6 +15,9 @@ struct DevTables {
   const double *leaf_frag, *p2m_frag;
   const double *leaf_mass;   // [54][KMAX] mass-row weights of the leaf operators
   int leaf_kmax;
+  // split (BF16-slice) near tables and their row-type scales (split contexts only)
+  const uint16_t *near_bf16;
+  double split_scale_v, split_scale_d;
   // M2M 4 x [2KP][2KP] and L2L 4 x [2KP][2KP] on interleaved coefficients, and
   // P2L per X configuration [2KP + mass row, padded][P], all fragment-major.
   const double *m2m_frag, *l2l_frag, *p2l_frag;
@@ -54,6 +57,7 @@ struct DevTree {
   const int *slot_type;    // [n_slots] 0: samples f of a source leaf (K = P); 1: local expansion
                            // of the target's box; 2: multipole of a source box (K = 2 KP)
   const int *slot_src;     // [n_slots][64] leaf or box index, -1 = none
+  const int *tile_nsl;     // [n_tiles] BF16 slices of the near tables (split contexts; tiles of one level)
 };
 
 // Expansion storage: [n_rhs][NB][KP] complex (interleaved re, im).
@@ -69,5 +73,9 @@ void launch_l2l(const DevTables &t, const DevTree &g, const int *boxes, int nbox
 // Near tables + L2T + W list for every leaf: writes V and G.
 void launch_leaf(const DevTables &t, const DevTree &g, const double *f, int nrhs, const double *M,
                  const double *L, double *V, double *G, hipStream_t s);
+// Split-precision variant: near tables as exact BF16 slice products; fscale
+// [n_rhs][N_L] receives each leaf's power-of-two scale (>= max |f|).
+void launch_leaf_split(const DevTables &t, const DevTree &g, const double *f, double *fscale, int nrhs,
+                       const double *M, const double *L, double *V, double *G, hipStream_t s);
 
 }  // namespace bx

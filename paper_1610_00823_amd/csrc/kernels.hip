@@ -13,6 +13,7 @@ namespace bx {
 namespace {
 
 constexpr double kInv2Pi = 0.15915494309189533577;
+constexpr int NOFF_DEV = 49;   // 7 x 7 same-level offsets (the V-list classes among them)
 
 __device__ inline double box_h(double width, int level) { return ldexp(width, -level); }
 
@@ -178,14 +179,24 @@ __global__ void __launch_bounds__(256) p2m_mfma_kernel(DevTables t, DevTree g, c
 // y_k = a~_k (-d/2)^-k, for the V list of each box.  H (KP x KP, real, the same
 // for every offset) stays in registers as MFMA A fragments; the B columns are
 // (source, Re/Im) pairs, 8 sources per 16 columns.  One wave per target box;
-// writes (initialises) every box's local expansion.
+// the power tables of the 49 offsets sit in LDS, and the next 8 sources'
+// multipoles are loaded while the current ones are multiplied.  Writes
+// (initialises) every box's local expansion.
 template <int KPT>
 __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, const double *__restrict__ M,
                                                        double *__restrict__ L) {
   constexpr int MT = KPT / 16, KS = KPT / 4;
+  __shared__ double2 spw[2][NOFF_DEV * KPT];
+  __shared__ double slogd[NOFF_DEV];
+  for (int i = threadIdx.x; i < NOFF_DEV * KPT; i += 256) {
+    spw[0][i] = ((const double2 *)t.pw_src)[i];
+    spw[1][i] = ((const double2 *)t.pw_tgt)[i];
+  }
+  if (threadIdx.x < NOFF_DEV) slogd[threadIdx.x] = t.logd[threadIdx.x];
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4, part = col & 1;
   const int box = blockIdx.x * 4 + wave;
-  if (box >= g.n_boxes) return;
+  if (box >= g.n_boxes) return;                 // no barrier follows
   const int rhs = blockIdx.y;
   const double *Mr = M + (size_t)rhs * g.n_boxes * KPT * 2;
   double hA[MT][KS];
@@ -201,20 +212,42 @@ __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, c
   double a0 = 0.0;
   const double logh = log(box_h(g.width, g.lvl[box]));
   const int e0 = g.v_ptr[box], e1 = g.v_ptr[box + 1];
-  for (int e = e0; e < e1; e += 8) {
+  // Two-stage pipeline over groups of 8 sources (this lane: source e + col/2):
+  // the data of group g+1 and the indices of group g+2 are requested before
+  // group g is multiplied.
+  auto idx = [&](int e, int &s_, int &o_, bool &ok_) {
     const int pe = e + (col >> 1);
-    const bool ok = pe < e1;
-    const int s = ok ? g.v_src[pe] : 0, o = ok ? g.v_cfg[pe] : 0;
-    const double2 *ap = (const double2 *)(Mr + (size_t)s * KPT * 2) + kq * KS;
-    const double2 *wp = (const double2 *)(t.pw_src + (size_t)o * KPT * 2) + kq * KS;
+    ok_ = pe < e1;
+    const int pc = ok_ ? pe : (e1 > 0 ? e1 - 1 : 0);   // always a valid entry: the loads are unconditional
+    s_ = g.v_src[pc];
+    o_ = g.v_cfg[pc];
+  };
+  auto data = [&](int s_, double2 *dst) {
+    const double2 *ap = (const double2 *)(Mr + (size_t)s_ * KPT * 2) + kq * KS;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) dst[ks] = ap[ks];
+  };
+  int s_c, o_c, s_n, o_n;
+  bool ok_c, ok_n;
+  double2 av[KS];
+  idx(e0, s_c, o_c, ok_c);
+  data(s_c, av);
+  idx(e0 + 8, s_n, o_n, ok_n);
+  for (int e = e0; e < e1; e += 8) {
+    double2 an[KS];
+    data(s_n, an);                                 // group g+1
+    int s_nn, o_nn;
+    bool ok_nn;
+    idx(e + 16, s_nn, o_nn, ok_nn);                // group g+2
     double bv[KS];
+    const double2 *wp = &spw[0][o_c * KPT + kq * KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const double2 a = ap[ks], w = wp[ks];
+      const double2 a = av[ks], w = wp[ks];
       const double y = part ? a.x * w.y + a.y * w.x : a.x * w.x - a.y * w.y;
-      bv[ks] = ok ? y : 0.0;
+      bv[ks] = ok_c ? y : 0.0;
     }
-    if (ok && part == 0 && kq == 0) a0 += Mr[(size_t)s * KPT * 2] * (logh + t.logd[o]);
+    a0 += (ok_c && part == 0 && kq == 0) ? av[0].x * (logh + slogd[o_c]) : 0.0;
     dbl4 c[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) c[m] = dbl4{0, 0, 0, 0};
@@ -222,7 +255,7 @@ __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, c
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int m = 0; m < MT; ++m) c[m] = mfma4(hA[m][ks], bv[ks], c[m]);
-    const double2 *qp = (const double2 *)(t.pw_tgt + (size_t)o * KPT * 2);
+    const double2 *qp = &spw[1][o_c * KPT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -231,8 +264,12 @@ __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, c
         const double zr = part ? zo : z, zi = part ? z : zo;
         const double2 q = qp[m * 16 + 4 * r + kq];
         const double v = part ? zr * q.y + zi * q.x : zr * q.x - zi * q.y;
-        acc[m][r] += ok ? v : 0.0;
+        acc[m][r] += ok_c ? v : 0.0;
       }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) av[ks] = an[ks];
+    s_c = s_n; o_c = o_n; ok_c = ok_n;
+    s_n = s_nn; o_n = o_nn; ok_n = ok_nn;
   }
   // sum over the 8 sources of each column group (lanes with equal kq and part)
 #pragma unroll
@@ -341,9 +378,28 @@ __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree 
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[i][nt] = dbl4{0, 0, 0, 0};
   double mpart = 0.0;
+  const int MTP = (MTR + 3) / 4 * 4;                // row tiles in the (padded) operator tables
+  // A fragment of row tile i, k-step ks of chunk c of slot sl (every index valid:
+  // the tables are padded to whole groups of row tiles)
+  auto a_ptr = [&](int sl_, int c_) -> const double * {
+    const int NC_ = (slot_type[sl_] == 0 ? P : K2) / KC;
+    return leaf_frag + slot_aoff[sl_] + ((size_t)(mtg + wave) * NC_ + c_) * KSC * 64 + lane;
+  };
+  auto a_stride = [&](int sl_) -> size_t {          // from row tile i to i + 1 (4 tiles apart)
+    const int NC_ = (slot_type[sl_] == 0 ? P : K2) / KC;
+    return (size_t)4 * NC_ * KSC * 64;
+  };
+  (void)MTP;
   Regs<PERT> rb;
+  double an[TPW];
   int sl = s0, c = 0, buf = 0;
-  if (sl < s1) rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, sl, 0, P, K2, sq, sinv_h2);
+  if (sl < s1) {
+    rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, sl, 0, P, K2, sq, sinv_h2);
+    const double *A0 = a_ptr(sl, 0);
+    const size_t st0 = a_stride(sl);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) an[i] = A0[i * st0];
+  }
   while (sl < s1) {
     const int K = slot_type[sl] == 0 ? P : K2, NC = K / KC;
     {   // stage this chunk's B columns and add their mass weights
@@ -356,19 +412,25 @@ __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree 
       }
     }
     __syncthreads();
-    const double *A = leaf_frag + slot_aoff[sl] + (size_t)c * KSC * 64;
     int nsl = sl, nc = c + 1;
     if (nc >= NC) { ++nsl; nc = 0; }
-    if (nsl < s1)                                  // next chunk in flight during the MFMAs
-      rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, nsl, nc, P, K2, sq, sinv_h2);
+    const double *Ac = a_ptr(sl, c);
+    const size_t stc = a_stride(sl);
     const double *S = sB[buf];
-#pragma unroll 4
+#pragma unroll
     for (int ks = 0; ks < KSC; ++ks) {
       double a[TPW];
 #pragma unroll
-      for (int i = 0; i < TPW; ++i) {
-        const int mt = mtg + wave + 4 * i;
-        a[i] = mt < MTR ? A[((size_t)mt * NC * KSC + ks) * 64 + lane] : 0.0;
+      for (int i = 0; i < TPW; ++i) a[i] = an[i];
+      if (ks + 1 < KSC) {                          // next k-step's fragments
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) an[i] = Ac[i * stc + (ks + 1) * 64];
+      } else if (nsl < s1) {                       // next chunk: its first fragments, then its B values
+        const double *An = a_ptr(nsl, nc);
+        const size_t stn = a_stride(nsl);
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) an[i] = An[i * stn];
+        rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, nsl, nc, P, K2, sq, sinv_h2);
       }
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
@@ -400,7 +462,242 @@ __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree 
       if (mt >= MTR) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = mt * 16 + 4 * r + kq;
+        const int row = mt * 16 + 4 * kq + r;        // the A rows of each tile are permuted to match
+        if (row < P) Vt[row] = h * h * acc[i][nt][r] + lg;
+        else Gt[row - P] = h * acc[i][nt][r];
+      }
+    }
+  }
+}
+
+
+// ------------------------------------------- split-precision leaf evaluation
+// As leaf_mfma_kernel, but the near-table slots run as exact BF16 slice
+// products.  A table value is sum_a t_a 2^(Et - 8(a+1)) and a sample
+// sum_b s_b 2^(Ef - 8(b+1)), integers |t_a|, |s_b| <= 256 stored with their
+// scales (exact in BF16; Et per row type, Ef per source leaf).  Within one slot
+// every product of slice group d = a + b has the same scale, and a 32-term
+// v_mfma_f32_16x16x32_bf16 sum of them is an integer below 2^22 times that
+// scale: exact in FP32 (a group of d+1 pairs over 64 k stays below 2^24 for
+// d <= 3; later groups lie below 2^-24 of the result).  Each group's sum is
+// added to the FP64 accumulator when the group is complete (groups of
+// different scales are never mixed in one FP32 sum: the MFMA accumulation of
+// such mixtures was measured to lose about 2^-33).  S per tile and row type
+// comes from the tile's level.  L2T, W, the mass (log h) term and all scalings stay FP64.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+__device__ inline flt4 mfma_bf16(bf16x8 a, bf16x8 b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// power-of-two scale 2^e >= max |f| of each leaf (1 for an all-zero leaf)
+__global__ void __launch_bounds__(64) leaf_scale_kernel(const double *__restrict__ f, int P, int n_leaves,
+                                                        double *__restrict__ fscale) {
+  const int leaf = blockIdx.x, rhs = blockIdx.y;
+  const double *fl = f + ((size_t)rhs * n_leaves + leaf) * P;
+  double m = 0.0;
+  for (int j = threadIdx.x; j < P; j += 64) m = fmax(m, fabs(fl[j]));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (threadIdx.x == 0) {
+    int e = 0;
+    frexp(m, &e);
+    fscale[(size_t)rhs * n_leaves + leaf] = m > 0.0 ? ldexp(1.0, e) : 1.0;
+  }
+}
+
+__device__ inline uint32_t bf16_bits(double v) { return __float_as_uint((float)v) >> 16; }
+
+template <int TPW, int KC>
+__global__ void __launch_bounds__(256, 1) leaf_split_kernel(DevTables t, DevTree g, const double *__restrict__ f,
+                                                            const double *__restrict__ fscale,
+                                                            const double *__restrict__ M,
+                                                            const double *__restrict__ L, double *__restrict__ V,
+                                                            double *__restrict__ G) {
+  constexpr int SMAX = 6, PERT = KC / 4, SB = KC + 1, SBH = KC + 8, NST = KC / 32, KSC = KC / 4;
+  constexpr int BYTES64 = LEAF_TILE * SB * 8, BYTES16 = SMAX * LEAF_TILE * SBH * 2;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[BYTES64 > BYTES16 ? BYTES64 : BYTES16];
+  __shared__ double sMass[LEAF_TILE];
+  double *sB = (double *)smem;
+  uint16_t *sH = (uint16_t *)smem;
+  const int tile = xcd_block(blockIdx.x, g.n_tiles);
+  if (tile < 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
+  const int rhs = blockIdx.z, P = t.P, K2 = 2 * t.KP, MTR = 3 * P / 16, NCU = P / KC;
+  const int mtg = blockIdx.y * 4 * TPW;
+  const int s0 = g.tile_ptr[tile], s1 = g.tile_ptr[tile + 1];
+  const int nsl_v = g.tile_nsl[tile] & 255, nsl_d = g.tile_nsl[tile] >> 8;
+  const int nsl = nsl_v > nsl_d ? nsl_v : nsl_d;
+  const double *fr = f + (size_t)rhs * g.n_leaves * P;
+  const double *fs = fscale + (size_t)rhs * g.n_leaves;
+  const double *Lr = L + (size_t)rhs * g.n_boxes * K2, *Mr = M + (size_t)rhs * g.n_boxes * K2;
+  const int *slot_type = g.slot_type, *slot_op = g.slot_op, *slot_aoff = g.slot_aoff;
+  const double *leaf_frag = t.leaf_frag, *leaf_mass = t.leaf_mass;
+  const int kmax = t.leaf_kmax;
+  const int scol = threadIdx.x >> 2, sq = threadIdx.x & 3;
+  const int stgt = g.tile_tgt[tile * LEAF_TILE + scol];
+  const double sinv_h2 = stgt >= 0 ? 1.0 / (box_h(g.width, g.leaf_level[stgt]) * box_h(g.width, g.leaf_level[stgt]))
+                                   : 0.0;
+  const int *slot_src = g.slot_src + scol;
+  int tns[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) tns[i] = (mtg + wave + 4 * i) * 16 < P ? nsl_v : nsl_d;
+  const uint4 *Ab = (const uint4 *)t.near_bf16;
+  // A slice fragments of row tile i (rows beyond the tables read tile 0: zero work is masked later)
+  auto a_base = [&](int op, int a, int i, int c_) -> size_t {
+    const int mt = mtg + wave + 4 * i;
+    return ((((size_t)op * SMAX + a) * MTR + (mt < MTR ? mt : 0)) * NCU + c_) * NST * 64 + lane;
+  };
+
+  dbl4 acc[TPW][4];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[i][nt] = dbl4{0, 0, 0, 0};
+  double mpart = 0.0;
+  Regs<PERT> rb;
+  int sl = s0, c = 0;
+  if (sl < s1) rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, sl, 0, P, K2, sq, sinv_h2);
+  while (sl < s1) {
+    const int type = slot_type[sl], K = type == 0 ? P : K2, NC = K / KC;
+    __syncthreads();                               // the previous chunk's readers are done
+    {
+      const double *mw = leaf_mass + (size_t)slot_op[sl] * kmax + c * KC + sq * PERT;
+#pragma unroll
+      for (int j = 0; j < PERT; ++j) mpart = fma(mw[j], rb.v[j], mpart);
+      if (type == 0) {   // samples: slices with their true scales 2^(Ef - 8(b+1))
+        const int src = slot_src[sl * LEAF_TILE];
+        const double sc = src >= 0 ? fs[src] : 1.0, inv = src >= 0 ? 1.0 / sc : 0.0;
+        double r[PERT];
+#pragma unroll
+        for (int j = 0; j < PERT; ++j) r[j] = rb.v[j] * inv;
+        double p2 = sc;
+        for (int b = 0; b < nsl; ++b) {
+          p2 *= 1.0 / 256.0;
+          uint4 *dst = (uint4 *)(sH + ((size_t)b * LEAF_TILE + scol) * SBH + sq * PERT);
+#pragma unroll
+          for (int j8 = 0; j8 < PERT / 8; ++j8) {
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              uint32_t hv[2];
+#pragma unroll
+              for (int e = 0; e < 2; ++e) {
+                const int j = j8 * 8 + 2 * q + e;
+                const double v = r[j] * 256.0, tr = trunc(v);
+                r[j] = v - tr;
+                hv[e] = bf16_bits(tr * p2);
+              }
+              w[q] = hv[0] | (hv[1] << 16);
+            }
+            dst[j8] = make_uint4(w[0], w[1], w[2], w[3]);
+          }
+        }
+      } else {
+        double *dst = sB + scol * SB + sq * PERT;
+#pragma unroll
+        for (int j = 0; j < PERT; ++j) dst[j] = rb.v[j];
+      }
+    }
+    __syncthreads();
+    int nsl2 = sl, nc = c + 1;
+    if (nc >= NC) { ++nsl2; nc = 0; }
+    if (nsl2 < s1) rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, nsl2, nc, P, K2, sq, sinv_h2);
+    if (type == 0) {
+      // slice pairs (a, b) in order of d = a + b; one exact FP32 sum per group d
+      const int op = slot_op[sl];
+      flt4 g32[TPW][4];
+#pragma unroll
+      for (int i = 0; i < TPW; ++i)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) g32[i][nt] = flt4{0, 0, 0, 0};
+      uint4 an[TPW][NST];
+#pragma unroll
+      for (int i = 0; i < TPW; ++i)
+#pragma unroll
+        for (int st = 0; st < NST; ++st) an[i][st] = Ab[a_base(op, 0, i, c) + st * 64];
+#pragma unroll
+      for (int pi = 0; pi < SMAX * (SMAX + 1) / 2; ++pi) {
+        // pair pi: group d, a = pi - d(d+1)/2, b = d - a
+        int d = 0;
+        while ((d + 1) * (d + 2) / 2 <= pi) ++d;
+        const int a = pi - d * (d + 1) / 2, b = d - a;
+        if (d >= nsl) break;
+        bf16x8 av[TPW][NST];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i)
+#pragma unroll
+          for (int st = 0; st < NST; ++st) av[i][st] = __builtin_bit_cast(bf16x8, an[i][st]);
+        {   // next pair's table slice in flight
+          int d2 = 0;
+          while ((d2 + 1) * (d2 + 2) / 2 <= pi + 1) ++d2;
+          const int a2 = pi + 1 - d2 * (d2 + 1) / 2;
+          if (pi + 1 < SMAX * (SMAX + 1) / 2 && d2 < nsl) {
+#pragma unroll
+            for (int i = 0; i < TPW; ++i)
+#pragma unroll
+              for (int st = 0; st < NST; ++st) an[i][st] = Ab[a_base(op, a2, i, c) + st * 64];
+          }
+        }
+#pragma unroll
+        for (int st = 0; st < NST; ++st)
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) {
+            const uint4 u = *(const uint4 *)(sH + ((size_t)b * LEAF_TILE + nt * 16 + col) * SBH + st * 32 + kq * 8);
+            const bf16x8 bv = __builtin_bit_cast(bf16x8, u);
+#pragma unroll
+            for (int i = 0; i < TPW; ++i)
+              if (d < tns[i]) g32[i][nt] = mfma_bf16(av[i][st], bv, g32[i][nt]);
+          }
+        if (a == d) {   // last pair of group d: add its exact sum
+#pragma unroll
+          for (int i = 0; i < TPW; ++i)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc[i][nt][r] += (double)g32[i][nt][r];
+              g32[i][nt] = flt4{0, 0, 0, 0};
+            }
+        }
+      }
+    } else {
+      const double *A = leaf_frag + slot_aoff[sl];
+#pragma unroll 4
+      for (int ks = 0; ks < KSC; ++ks) {
+        double av[TPW];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i)
+          av[i] = A[(((size_t)(mtg + wave + 4 * i) * NC + c) * KSC + ks) * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const double b = sB[(nt * 16 + col) * SB + kq * KSC + ks];
+#pragma unroll
+          for (int i = 0; i < TPW; ++i) acc[i][nt] = mfma4(av[i], b, acc[i][nt]);
+        }
+      }
+    }
+    sl = nsl2;
+    c = nc;
+  }
+  mpart += __shfl_xor(mpart, 1);
+  mpart += __shfl_xor(mpart, 2);
+  if (sq == 0) sMass[scol] = mpart;
+  __syncthreads();
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int tgt = g.tile_tgt[tile * LEAF_TILE + nt * 16 + col];
+    if (tgt < 0) continue;
+    const double h = box_h(g.width, g.leaf_level[tgt]);
+    const double lg = h * h * log(h) * kInv2Pi * sMass[nt * 16 + col];
+    double *Vt = V + ((size_t)rhs * g.n_leaves + tgt) * P;
+    double *Gt = G + ((size_t)rhs * g.n_leaves + tgt) * 2 * P;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int mt = mtg + wave + 4 * i;
+      if (mt >= MTR) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = mt * 16 + 4 * kq + r;
         if (row < P) Vt[row] = h * h * acc[i][nt][r] + lg;
         else Gt[row - P] = h * acc[i][nt][r];
       }
@@ -454,6 +751,17 @@ void launch_leaf(const DevTables &t, const DevTree &g, const double *f, int nrhs
     hipLaunchKernelGGL((leaf_mfma_kernel<3, 64>), dim3(bx, 1, nrhs), dim3(256), 0, s, t, g, f, M, L, V, G);
   } else {                // 48 row tiles: 3 groups of 16, 4 per wave
     hipLaunchKernelGGL((leaf_mfma_kernel<4, 64>), dim3(bx, 3, nrhs), dim3(256), 0, s, t, g, f, M, L, V, G);
+  }
+}
+
+void launch_leaf_split(const DevTables &t, const DevTree &g, const double *f, double *fscale, int nrhs,
+                       const double *M, const double *L, double *V, double *G, hipStream_t s) {
+  hipLaunchKernelGGL(leaf_scale_kernel, dim3(g.n_leaves, nrhs), dim3(64), 0, s, f, t.P, g.n_leaves, fscale);
+  const int bx = (g.n_tiles + 7) / 8 * 8;
+  if (t.n == 8) {
+    hipLaunchKernelGGL((leaf_split_kernel<3, 64>), dim3(bx, 1, nrhs), dim3(256), 0, s, t, g, f, fscale, M, L, V, G);
+  } else {
+    hipLaunchKernelGGL((leaf_split_kernel<4, 64>), dim3(bx, 3, nrhs), dim3(256), 0, s, t, g, f, fscale, M, L, V, G);
   }
 }
 

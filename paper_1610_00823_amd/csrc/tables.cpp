@@ -471,7 +471,7 @@ int build_tables(Tables &T, int n, int p, double tol, int nthreads) {
 LeafFragLayout leaf_frag_layout(int n, int p) {
   LeafFragLayout L;
   const int P = n * n, KP = (p + 1 + 15) / 16 * 16;
-  L.MTR = 3 * P / 16;
+  L.MTR = (3 * P / 16 + 3) / 4 * 4;                // padded to whole groups of 4 row tiles
   L.KC = std::min(64, P);
   L.KMAX = std::max(P, 2 * KP);
   L.near0 = 0;
@@ -487,12 +487,15 @@ namespace {
 // Append the MFMA A fragments of a rows x K matrix (element (i, k) = a(i, k)),
 // row tiles of 16, K in chunks of KC, within a chunk k = (lane / 16) * KSC + ks.
 template <class F>
-void append_frag_chunked(std::vector<double> &out, int MT, int K, int KC, F a) {
+void append_frag_chunked(std::vector<double> &out, int MT, int K, int KC, F a, bool permute_rows = false) {
   const int NC = K / KC, KSC = KC / 4;
   for (int mt = 0; mt < MT; ++mt)
     for (int c = 0; c < NC; ++c)
       for (int ks = 0; ks < KSC; ++ks)
-        for (int lane = 0; lane < 64; ++lane) out.push_back(a(mt * 16 + (lane & 15), c * KC + (lane >> 4) * KSC + ks));
+        for (int lane = 0; lane < 64; ++lane) {
+          const int m = lane & 15, row = permute_rows ? 4 * (m % 4) + m / 4 : m;
+          out.push_back(a(mt * 16 + row, c * KC + (lane >> 4) * KSC + ks));
+        }
 }
 template <class F>
 void append_frag(std::vector<double> &out, int MT, int K, F a) {
@@ -508,26 +511,88 @@ void build_leaf_frag(const Tables &T, std::vector<double> &out, std::vector<doub
   mass.assign((size_t)(NCFG_U + 1 + NCFG_W) * L.KMAX, 0.0);
   for (int c = 0; c < NCFG_U; ++c) {
     const double *A = &T.near_[(size_t)c * MR * P];
-    append_frag_chunked(out, L.MTR, P, L.KC, [&](int i, int k) { return A[(size_t)i * P + k]; });
+    append_frag_chunked(out, L.MTR, P, L.KC, [&](int i, int k) { return i < 3 * P ? A[(size_t)i * P + k] : 0.0; },
+                        true);
     for (int k = 0; k < P; ++k) mass[(size_t)c * L.KMAX + k] = A[(size_t)3 * P * P + k];
   }
   // expansion columns are stored interleaved (Re b_m, Im b_m) as in device memory
   append_frag_chunked(out, L.MTR, K2, L.KC, [&](int i, int k) {
-    return T.l2t[(size_t)i * K2 + (k & 1) * KP + k / 2];
-  });
+    return i < 3 * P ? T.l2t[(size_t)i * K2 + (k & 1) * KP + k / 2] : 0.0;
+  }, true);
   // W: V rows carry log|e| - log 2 in the a_0 column (log(h/2) = log h - log 2, the
   // log h part comes through the mass weight on a_0), gradient rows are doubled (1/(h/2)).
   const double log2_2pi = std::log(2.0) / (2 * 3.14159265358979323846);
   for (int c = 0; c < NCFG_W; ++c) {
     const double *A = &T.m2t[(size_t)c * 3 * P * K2];
     append_frag_chunked(out, L.MTR, K2, L.KC, [&](int i, int k) {
+      if (i >= 3 * P) return 0.0;
       double v = A[(size_t)i * K2 + (k & 1) * KP + k / 2];
       if (i < P && k == 0) v -= log2_2pi;
       if (i >= P) v *= 2.0;
       return v;
-    });
+    }, true);
     mass[(size_t)(NCFG_U + 1 + c) * L.KMAX + 0] = 1.0;
   }
+}
+
+static uint16_t bf16_bits_scaled(double v, double pow2) {
+  // v is an integer with |v| <= 256 and pow2 a power of two: v * pow2 is exact in
+  // float and in BF16 (the upper half of the float) while it stays a normal number
+  float f = (float)(v * pow2);
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return (uint16_t)(u >> 16);
+}
+
+void build_split_tables(const Tables &T, SplitTables &S) {
+  const LeafFragLayout L = leaf_frag_layout(T.n, T.p);
+  const int P = T.P, MR = T.MR, KC = L.KC, NC = P / KC, MTR = 3 * P / 16;
+  double mv = 0.0, md = 0.0;
+  for (int c = 0; c < NCFG_U; ++c)
+    for (int i = 0; i < 3 * P; ++i)
+      for (int k = 0; k < P; ++k) {
+        double v = std::fabs(T.near_[((size_t)c * MR + i) * P + k]);
+        if (i < P) mv = std::max(mv, v); else md = std::max(md, v);
+      }
+  int ev, ed;
+  std::frexp(mv, &ev);
+  std::frexp(md, &ed);
+  S.scale_v = std::ldexp(1.0, ev);
+  S.scale_d = std::ldexp(1.0, ed);
+  // error bound factor: a target's near field uses at most 13 configurations, each K terms
+  S.bound_v = 13.0 * P * S.scale_v;
+  S.bound_d = 13.0 * P * S.scale_d;
+  S.a.assign((size_t)NCFG_U * SPLIT_SMAX * MTR * NC * 2 * 64 * 8, 0);
+  for (int c = 0; c < NCFG_U; ++c)
+    for (int mt = 0; mt < MTR; ++mt)
+      for (int ch = 0; ch < NC; ++ch)
+        for (int st = 0; st < 2; ++st)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int e = 0; e < 8; ++e) {
+              const int row = mt * 16 + (lane & 15), k = ch * KC + st * 32 + (lane >> 4) * 8 + e;
+              const double E = row < P ? S.scale_v : S.scale_d;
+              double r = k < P ? T.near_[((size_t)c * MR + row) * P + k] / E : 0.0;
+              for (int a = 0; a < SPLIT_SMAX; ++a) {
+                const double sc = r * 256.0, sl = std::trunc(sc);
+                r = sc - sl;
+                // slice with its true scale: an integer times a power of two, exact in BF16
+                S.a[((((((size_t)c * SPLIT_SMAX + a) * MTR + mt) * NC + ch) * 2 + st) * 64 + lane) * 8 + e] =
+                    bf16_bits_scaled(sl, E * std::ldexp(1.0, -8 * (a + 1)));
+              }
+            }
+}
+
+int split_slices(const SplitTables &S, int level, double tol, bool grad_rows) {
+  // truncating x and y to S slices and dropping slice pairs with a + b >= S
+  // leaves at most (S + 1) 2^-8S 2^(Ex + Ey) per product term; V rows carry h^2,
+  // gradient rows h
+  const double h = std::ldexp(1.0, -level);
+  for (int s = 1; s <= SPLIT_SMAX; ++s) {
+    const double e = (s + 1) * std::ldexp(1.0, -8 * s);
+    if (!grad_rows && h * h * S.bound_v * 2.0 * e <= tol) return s;
+    if (grad_rows && h * S.bound_d * 2.0 * e <= tol) return s;
+  }
+  return SPLIT_SMAX;
 }
 
 void build_p2m_frag(const Tables &T, std::vector<double> &out) {

@@ -159,3 +159,57 @@ def test_graph_replays_match_eager(ctx8):
         torch.cuda.synchronize()
         assert float(junk) == float(junk)
         assert torch.equal(V, Ve) and torch.equal(G, Ge), f"replay {rep} differs"
+
+
+# ---------------------------------------------------------------- split BF16
+SPLIT_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx8s():
+    _torch()
+    return B.Context(8, 30, B.BX_SPLIT_BF16)
+
+
+@pytest.mark.parametrize("case", ["uniform4_gauss", "graded_random"])
+def test_split_precision_all_nodes(ctx8s, case):
+    # Near tables as exact BF16 slice products (FP32 accumulation, FP64
+    # recombination): every result within 1e-10 of the oracle (relative L-inf).
+    if case == "uniform4_gauss":
+        t, src = I.workload("uniform4_gauss")
+        f = I.sample(t, src, 8)
+    else:
+        t = I.point_refined_tree([[0.3, 0.2], [-0.26, -0.4], [0.45, -0.45], [-0.1, 0.33]], [5, 4, 6, 3])
+        f = np.random.default_rng(5).standard_normal((t.n_leaves, 8, 8))
+    V, G, tr = gpu_eval(ctx8s, t, f)
+    assert tr.query("split_products") > 0
+    check_vs_oracle(t, f, V[0], G[0], tol=SPLIT_TOL)
+
+
+def test_split_precision_adaptive_sampled(ctx8s):
+    t, src = I.workload("gauss20_s0")
+    f = I.sample(t, src, 8)
+    V, G, _ = gpu_eval(ctx8s, t, f)
+    rng = np.random.default_rng(1)
+    sel = []
+    for l in np.unique(t.level):
+        idx = np.flatnonzero(t.level == l)
+        sel += list(rng.choice(idx, min(len(idx), 6), replace=False))
+    sel = np.array(sorted(sel))
+    Vo, Gxo, Gyo = oracle.volume_at_nodes(t.level, t.ix, t.iy, f, leaves=sel)
+    ev = np.abs(V[0][sel] - Vo).max() / np.abs(V[0]).max()
+    ex = np.abs(G[0][sel, 0] - Gxo).max() / np.abs(G[0][:, 0]).max()
+    ey = np.abs(G[0][sel, 1] - Gyo).max() / np.abs(G[0][:, 1]).max()
+    print(f"split, sampled {len(sel)} leaves: E(V)={ev:.2e} E(dV/dx1)={ex:.2e} E(dV/dx2)={ey:.2e}")
+    assert ev < SPLIT_TOL and ex < SPLIT_TOL and ey < SPLIT_TOL
+
+
+def test_split_multi_rhs_equals_single(ctx8s):
+    torch = _torch()
+    t = I.point_refined_tree([[0.2, -0.3]], [4])
+    f = np.random.default_rng(19).standard_normal((2, t.n_leaves, 8, 8))
+    tr = B.Tree.from_inputs(ctx8s, t)
+    V2, G2 = B.volume_eval_grad(ctx8s, tr, torch.from_numpy(f).cuda())
+    for r in range(2):
+        V1, G1 = B.volume_eval_grad(ctx8s, tr, torch.from_numpy(f[r].copy()).cuda())
+        assert torch.equal(V1[0], V2[r]) and torch.equal(G1[0], G2[r])

@@ -301,3 +301,13 @@ def test_l2t_m2t_p2l_p2m_against_direct_sums():
     u = pts[:, 0] + 1j * pts[:, 1]
     Vl = np.array([(bl * uu ** np.arange(nt)).sum().real for uu in u]) / (2 * np.pi)
     assert np.abs(Vl - Vo).max() < 1e-12
+
+
+def test_split_slices_reconstruct_tables():
+    # The BF16 slices of the near tables: integers |s| <= 256, and
+    # scale * sum_a s_a 2^-8(a+1) reproduces every table entry to the truncation bound.
+    ctx = B.Context(8, 16, B.BX_SPLIT_BF16 | B.BX_HOST_ONLY)
+    tr = B.Tree.from_inputs(ctx, I.point_refined_tree([[0.3, 0.2]], [6]))
+    assert tr.query("split_products") >= 1
+    with pytest.raises(B.BoxFMMError):
+        B.Context(4, 16, B.BX_SPLIT_BF16 | B.BX_HOST_ONLY, build=False)
