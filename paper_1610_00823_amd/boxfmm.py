@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libboxfmm.so")
+# BOXFMM_LIB names another build of the same library (side-by-side builds)
+LIB_PATH = os.environ.get("BOXFMM_LIB") or os.path.join(HERE, "libboxfmm.so")
 
 BX_OK = 0
 BX_E_ARG, BX_E_NOT_BALANCED, BX_E_INVALID_TREE, BX_E_UNSUPPORTED, BX_E_HIP, BX_E_OOM, BX_E_NO_TABLES = (

@@ -13,6 +13,7 @@
 
 struct bx_ctx {
   int n = 0, p = 0, device = 0;
+  int n_cu = 256;                        // compute units of the device
   uint32_t flags = 0;
   double split_tol = 1e-11;              // slice-truncation tolerance of the split near tables
   bx::SplitTables split;
@@ -126,12 +127,18 @@ int bx_create(bx_ctx **out, int n_nodes, int p_exp, uint32_t flags) {
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   }
+  int n_cu = 256;
+  if (!(flags & BX_HOST_ONLY)) {
+    hipError_t e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  }
   bx_ctx *c = new (std::nothrow) bx_ctx;
   if (!c) return fail(BX_E_OOM, "bx_create");
   c->n = n_nodes;
   c->p = p_exp;
   c->flags = flags;
   c->device = dev;
+  c->n_cu = n_cu;
   *out = c;
   return BX_OK;
 }
@@ -192,6 +199,61 @@ int bx_build_tables(bx_ctx *ctx, double quad_tol, const char *cache_dir) {
   ctx->ready = true;
   return BX_OK;
 }
+
+namespace bx {
+namespace {
+// Work units of the leaf kernels, in launch order: (tile, first row tile | row
+// tiles per wave << 16), tile -1 for an empty block.  A unit costs about its
+// slot count times its rows.  Tiles far above the balanced share of one resident
+// block are split by rows (one row tile per wave), so that no single tile sets
+// the kernel's duration.  Each XCD (blocks are dealt to the 8 XCDs round-robin)
+// receives a contiguous range of tiles of equal total cost, for the L2 locality
+// of the operator tables, in decreasing unit cost: the dispatcher then runs
+// longest-first.
+void leaf_units(const std::vector<int> &tile_ptr, int n, int blocks_per_cu, int n_cu, std::vector<int> &unit_tile,
+                std::vector<int> &unit_mt) {
+  const int P = n * n, MTR = std::max(1, 3 * P / 16);
+  const int TPW = n == 4 ? 1 : (n == 8 ? 3 : 4), G = (MTR + 4 * TPW - 1) / (4 * TPW);
+  const int ntiles = (int)tile_ptr.size() - 1;
+  struct U { int tile, mt; double cost; };
+  auto cost_of = [](int slots, int ni) { return slots * (ni + 0.35); };
+  double total = 0;
+  for (int tt = 0; tt < ntiles; ++tt) total += G * cost_of(tile_ptr[tt + 1] - tile_ptr[tt], TPW);
+  const double share = total / std::max(1, blocks_per_cu * n_cu);
+  std::vector<U> units;
+  for (int tt = 0; tt < ntiles; ++tt) {
+    const int ns = tile_ptr[tt + 1] - tile_ptr[tt];
+    const bool heavy = TPW > 1 && cost_of(ns, TPW) > 1.25 * share;
+    for (int gg = 0; gg < G; ++gg) {
+      if (!heavy) units.push_back({tt, gg * 4 * TPW | TPW << 16, cost_of(ns, TPW)});
+      else
+        for (int j = 0; j < TPW; ++j) units.push_back({tt, (gg * 4 * TPW + 4 * j) | 1 << 16, cost_of(ns, 1)});
+    }
+  }
+  double sum = 0;
+  for (const U &u : units) sum += u.cost;
+  std::vector<std::vector<U>> part(8);
+  double run = 0;
+  for (const U &u : units) {
+    const int x = std::min(7, (int)(8.0 * run / std::max(sum, 1e-300)));
+    part[x].push_back(u);
+    run += u.cost;
+  }
+  size_t per = 0;
+  for (auto &v : part) {
+    std::stable_sort(v.begin(), v.end(), [](const U &a, const U &b) { return a.cost > b.cost; });
+    per = std::max(per, v.size());
+  }
+  unit_tile.assign(8 * per, -1);
+  unit_mt.assign(8 * per, 0);
+  for (int x = 0; x < 8; ++x)
+    for (size_t j = 0; j < part[x].size(); ++j) {
+      unit_tile[8 * j + x] = part[x][j].tile;
+      unit_mt[8 * j + x] = part[x][j].mt;
+    }
+}
+}  // namespace
+}  // namespace bx
 
 int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree **out, bx_stream_t stream) {
   if (!ctx || !trees || !out) return fail(BX_E_ARG, "bx_tree_upload: NULL argument");
@@ -296,6 +358,9 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
     tile_ptr[tt + 1] = (int)slot_type.size();
   }
   g.n_tiles = ntiles;
+  std::vector<int> unit_tile, unit_mt;
+  leaf_units(tile_ptr, ctx->n, split ? 1 : 2, ctx->n_cu, unit_tile, unit_mt);
+  g.n_units = (int)unit_tile.size();
   // X-list tiles: target boxes with X entries, sorted by configuration set
   std::vector<int> xb;
   std::vector<uint32_t> xsig(H.n_boxes, 0);
@@ -357,7 +422,8 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       (rc = upload(t->dev, tile_tgt, &g.tile_tgt, s)) || (rc = upload(t->dev, tile_ptr, &g.tile_ptr, s)) ||
       (rc = upload(t->dev, slot_aoff, &g.slot_aoff, s)) || (rc = upload(t->dev, slot_type, &g.slot_type, s)) ||
       (rc = upload(t->dev, slot_op, &g.slot_op, s)) || (rc = upload(t->dev, tile_nsl, &g.tile_nsl, s)) ||
-      (rc = upload(t->dev, slot_src, &g.slot_src, s))) {
+      (rc = upload(t->dev, slot_src, &g.slot_src, s)) || (rc = upload(t->dev, unit_tile, &g.unit_tile, s)) ||
+      (rc = upload(t->dev, unit_mt, &g.unit_mt, s))) {
     bx_tree_destroy(t);
     return rc;
   }

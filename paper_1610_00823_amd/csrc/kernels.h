@@ -58,6 +58,10 @@ struct DevTree {
                            // of the target's box; 2: multipole of a source box (K = 2 KP)
   const int *slot_src;     // [n_slots][64] leaf or box index, -1 = none
   const int *tile_nsl;     // [n_tiles] BF16 slices of the near tables (split contexts; tiles of one level)
+  // work units of the leaf kernels in launch order (one block each): tile (-1 =
+  // empty block) and first row tile | (row tiles per wave) << 16
+  int n_units;
+  const int *unit_tile, *unit_mt;
 };
 
 // Expansion storage: [n_rhs][NB][KP] complex (interleaved re, im).

@@ -186,11 +186,12 @@ template <int KPT>
 __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, const double *__restrict__ M,
                                                        double *__restrict__ L) {
   constexpr int MT = KPT / 16, KS = KPT / 4;
-  __shared__ double2 spw[2][NOFF_DEV * KPT];
+  constexpr int PWS = KPT + 1;                 // padded row: 8 offsets per column group, distinct banks
+  __shared__ double2 spw[2][NOFF_DEV * PWS];
   __shared__ double slogd[NOFF_DEV];
   for (int i = threadIdx.x; i < NOFF_DEV * KPT; i += 256) {
-    spw[0][i] = ((const double2 *)t.pw_src)[i];
-    spw[1][i] = ((const double2 *)t.pw_tgt)[i];
+    spw[0][i / KPT * PWS + i % KPT] = ((const double2 *)t.pw_src)[i];
+    spw[1][i / KPT * PWS + i % KPT] = ((const double2 *)t.pw_tgt)[i];
   }
   if (threadIdx.x < NOFF_DEV) slogd[threadIdx.x] = t.logd[threadIdx.x];
   __syncthreads();
@@ -240,7 +241,7 @@ __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, c
     bool ok_nn;
     idx(e + 16, s_nn, o_nn, ok_nn);                // group g+2
     double bv[KS];
-    const double2 *wp = &spw[0][o_c * KPT + kq * KS];
+    const double2 *wp = &spw[0][o_c * PWS + kq * KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const double2 a = av[ks], w = wp[ks];
@@ -255,7 +256,7 @@ __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, c
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int m = 0; m < MT; ++m) c[m] = mfma4(hA[m][ks], bv[ks], c[m]);
-    const double2 *qp = &spw[1][o_c * KPT];
+    const double2 *qp = &spw[1][o_c * PWS];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -311,16 +312,13 @@ __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, c
 // LDS once per block (double buffered through registers, one barrier per
 // chunk); wave w owns row tiles w, w+4, w+8, ... of its row group and all four
 // 16-leaf column tiles, so each A fragment read from the operator table feeds
-// four MFMAs.  grid.y splits the rows into groups of 4*TPW tiles.
+// four MFMAs.  Each block runs one work unit (tile, first row tile, row tiles
+// per wave): heavy tiles are split by rows over several blocks, and the host
+// orders the units so that each XCD gets a contiguous range, longest first.
 constexpr int LEAF_TILE = 64;
-
-// logical block index that gives each XCD (blocks are dealt round-robin to
-// the 8 XCDs) a contiguous range of tiles; -1 for padding blocks
-__device__ inline int xcd_block(int b, int nb_logical) {
-  const int per = (nb_logical + 7) / 8;
-  const int l = (b % 8) * per + b / 8;
-  return l < nb_logical ? l : -1;
-}
+#ifndef LEAF_PF
+#define LEAF_PF 2   // k-steps of A fragments in flight in the FP64 leaf GEMM
+#endif
 
 template <int N>
 struct Regs {
@@ -354,11 +352,17 @@ __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree 
   constexpr int KSC = KC / 4, PERT = KC / 4, SB = KC + 1;
   __shared__ double sB[2][LEAF_TILE * SB];
   __shared__ double sMass[LEAF_TILE];
-  const int tile = xcd_block(blockIdx.x, g.n_tiles);
+  const int tile = g.unit_tile[blockIdx.x];
   if (tile < 0) return;                        // whole block: no barrier is skipped
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
   const int rhs = blockIdx.z, P = t.P, K2 = 2 * t.KP, MTR = 3 * P / 16;
-  const int mtg = blockIdx.y * 4 * TPW;        // first row tile of this group
+  const int mtg = g.unit_mt[blockIdx.x] & 0xffff;   // first row tile of this unit
+  const int ni = g.unit_mt[blockIdx.x] >> 16;       // row tiles per wave (<= TPW)
+  // row tile of fragment i: i < ni computes; the others reread tile 0 (always in
+  // the table) and feed no MFMA
+  int ir[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) ir[i] = i < ni ? i : 0;
   const int s0 = g.tile_ptr[tile], s1 = g.tile_ptr[tile + 1];
   const double *fr = f + (size_t)rhs * g.n_leaves * P;
   const double *Lr = L + (size_t)rhs * g.n_boxes * K2, *Mr = M + (size_t)rhs * g.n_boxes * K2;
@@ -390,15 +394,22 @@ __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree 
     return (size_t)4 * NC_ * KSC * 64;
   };
   (void)MTP;
+  // A fragments run LEAF_PF k-steps ahead of the MFMAs (ring an[ks % LEAF_PF]);
+  // the next chunk's B columns are requested right after this chunk's barrier,
+  // so both latencies are covered by LEAF_PF k-steps of MFMA work.
+  constexpr int D = LEAF_PF < KSC ? LEAF_PF : KSC;
+  static_assert(KSC % D == 0, "prefetch depth must divide the chunk's k-steps");
   Regs<PERT> rb;
-  double an[TPW];
+  double an[D][TPW];
   int sl = s0, c = 0, buf = 0;
   if (sl < s1) {
-    rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, sl, 0, P, K2, sq, sinv_h2);
     const double *A0 = a_ptr(sl, 0);
     const size_t st0 = a_stride(sl);
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) an[i] = A0[i * st0];
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) an[j][i] = A0[ir[i] * st0 + j * 64];
+    rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, sl, 0, P, K2, sq, sinv_h2);
   }
   while (sl < s1) {
     const int K = slot_type[sl] == 0 ? P : K2, NC = K / KC;
@@ -414,29 +425,31 @@ __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree 
     __syncthreads();
     int nsl = sl, nc = c + 1;
     if (nc >= NC) { ++nsl; nc = 0; }
+    const bool more = nsl < s1;
     const double *Ac = a_ptr(sl, c);
     const size_t stc = a_stride(sl);
+    const double *An = more ? a_ptr(nsl, nc) : Ac;
+    const size_t stn = more ? a_stride(nsl) : stc;
+    if (more) rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, nsl, nc, P, K2, sq, sinv_h2);
     const double *S = sB[buf];
 #pragma unroll
     for (int ks = 0; ks < KSC; ++ks) {
       double a[TPW];
 #pragma unroll
-      for (int i = 0; i < TPW; ++i) a[i] = an[i];
-      if (ks + 1 < KSC) {                          // next k-step's fragments
+      for (int i = 0; i < TPW; ++i) a[i] = an[ks % D][i];
+      if (ks + D < KSC) {
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) an[i] = Ac[i * stc + (ks + 1) * 64];
-      } else if (nsl < s1) {                       // next chunk: its first fragments, then its B values
-        const double *An = a_ptr(nsl, nc);
-        const size_t stn = a_stride(nsl);
+        for (int i = 0; i < TPW; ++i) an[ks % D][i] = Ac[ir[i] * stc + (ks + D) * 64];
+      } else if (more) {
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) an[i] = An[i * stn];
-        rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, nsl, nc, P, K2, sq, sinv_h2);
+        for (int i = 0; i < TPW; ++i) an[ks % D][i] = An[ir[i] * stn + (ks + D - KSC) * 64];
       }
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
         const double b = S[(nt * 16 + col) * SB + kq * KSC + ks];
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) acc[i][nt] = mfma4(a[i], b, acc[i][nt]);
+        for (int i = 0; i < TPW; ++i)
+          if (i < ni) acc[i][nt] = mfma4(a[i], b, acc[i][nt]);
       }
     }
     sl = nsl;
@@ -459,7 +472,7 @@ __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree 
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int mt = mtg + wave + 4 * i;
-      if (mt >= MTR) continue;
+      if (i >= ni || mt >= MTR) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = mt * 16 + 4 * kq + r;        // the A rows of each tile are permuted to match
@@ -520,11 +533,11 @@ __global__ void __launch_bounds__(256, 1) leaf_split_kernel(DevTables t, DevTree
   __shared__ double sMass[LEAF_TILE];
   double *sB = (double *)smem;
   uint16_t *sH = (uint16_t *)smem;
-  const int tile = xcd_block(blockIdx.x, g.n_tiles);
+  const int tile = g.unit_tile[blockIdx.x];
   if (tile < 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
   const int rhs = blockIdx.z, P = t.P, K2 = 2 * t.KP, MTR = 3 * P / 16, NCU = P / KC;
-  const int mtg = blockIdx.y * 4 * TPW;
+  const int mtg = g.unit_mt[blockIdx.x] & 0xffff, ni = g.unit_mt[blockIdx.x] >> 16;
   const int s0 = g.tile_ptr[tile], s1 = g.tile_ptr[tile + 1];
   const int nsl_v = g.tile_nsl[tile] & 255, nsl_d = g.tile_nsl[tile] >> 8;
   const int nsl = nsl_v > nsl_d ? nsl_v : nsl_d;
@@ -541,11 +554,11 @@ __global__ void __launch_bounds__(256, 1) leaf_split_kernel(DevTables t, DevTree
   const int *slot_src = g.slot_src + scol;
   int tns[TPW];
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) tns[i] = (mtg + wave + 4 * i) * 16 < P ? nsl_v : nsl_d;
+  for (int i = 0; i < TPW; ++i) tns[i] = i >= ni ? 0 : ((mtg + wave + 4 * i) * 16 < P ? nsl_v : nsl_d);
   const uint4 *Ab = (const uint4 *)t.near_bf16;
   // A slice fragments of row tile i (rows beyond the tables read tile 0: zero work is masked later)
   auto a_base = [&](int op, int a, int i, int c_) -> size_t {
-    const int mt = mtg + wave + 4 * i;
+    const int mt = mtg + wave + 4 * (i < ni ? i : 0);
     return ((((size_t)op * SMAX + a) * MTR + (mt < MTR ? mt : 0)) * NCU + c_) * NST * 64 + lane;
   };
 
@@ -667,12 +680,13 @@ __global__ void __launch_bounds__(256, 1) leaf_split_kernel(DevTables t, DevTree
         double av[TPW];
 #pragma unroll
         for (int i = 0; i < TPW; ++i)
-          av[i] = A[(((size_t)(mtg + wave + 4 * i) * NC + c) * KSC + ks) * 64 + lane];
+          av[i] = A[(((size_t)(mtg + wave + 4 * (i < ni ? i : 0)) * NC + c) * KSC + ks) * 64 + lane];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
           const double b = sB[(nt * 16 + col) * SB + kq * KSC + ks];
 #pragma unroll
-          for (int i = 0; i < TPW; ++i) acc[i][nt] = mfma4(av[i], b, acc[i][nt]);
+          for (int i = 0; i < TPW; ++i)
+            if (i < ni) acc[i][nt] = mfma4(av[i], b, acc[i][nt]);
         }
       }
     }
@@ -694,7 +708,7 @@ __global__ void __launch_bounds__(256, 1) leaf_split_kernel(DevTables t, DevTree
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int mt = mtg + wave + 4 * i;
-      if (mt >= MTR) continue;
+      if (i >= ni || mt >= MTR) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = mt * 16 + 4 * kq + r;
@@ -744,24 +758,26 @@ void launch_l2l(const DevTables &t, const DevTree &g, const int *boxes, int nbox
 }
 void launch_leaf(const DevTables &t, const DevTree &g, const double *f, int nrhs, const double *M,
                  const double *L, double *V, double *G, hipStream_t s) {
-  const int bx = (g.n_tiles + 7) / 8 * 8;     // padded to a multiple of the 8 XCDs
+  if (g.n_units <= 0) return;
+  const dim3 grid(g.n_units, 1, nrhs);      // one work unit per block (a multiple of the 8 XCDs)
   if (t.n == 4) {         // 3 row tiles, K chunks of 16
-    hipLaunchKernelGGL((leaf_mfma_kernel<1, 16>), dim3(bx, 1, nrhs), dim3(256), 0, s, t, g, f, M, L, V, G);
+    hipLaunchKernelGGL((leaf_mfma_kernel<1, 16>), grid, dim3(256), 0, s, t, g, f, M, L, V, G);
   } else if (t.n == 8) {  // 12 row tiles: 3 per wave
-    hipLaunchKernelGGL((leaf_mfma_kernel<3, 64>), dim3(bx, 1, nrhs), dim3(256), 0, s, t, g, f, M, L, V, G);
-  } else {                // 48 row tiles: 3 groups of 16, 4 per wave
-    hipLaunchKernelGGL((leaf_mfma_kernel<4, 64>), dim3(bx, 3, nrhs), dim3(256), 0, s, t, g, f, M, L, V, G);
+    hipLaunchKernelGGL((leaf_mfma_kernel<3, 64>), grid, dim3(256), 0, s, t, g, f, M, L, V, G);
+  } else {                // 48 row tiles: groups of 16, 4 per wave
+    hipLaunchKernelGGL((leaf_mfma_kernel<4, 64>), grid, dim3(256), 0, s, t, g, f, M, L, V, G);
   }
 }
 
 void launch_leaf_split(const DevTables &t, const DevTree &g, const double *f, double *fscale, int nrhs,
                        const double *M, const double *L, double *V, double *G, hipStream_t s) {
   hipLaunchKernelGGL(leaf_scale_kernel, dim3(g.n_leaves, nrhs), dim3(64), 0, s, f, t.P, g.n_leaves, fscale);
-  const int bx = (g.n_tiles + 7) / 8 * 8;
+  if (g.n_units <= 0) return;
+  const dim3 grid(g.n_units, 1, nrhs);
   if (t.n == 8) {
-    hipLaunchKernelGGL((leaf_split_kernel<3, 64>), dim3(bx, 1, nrhs), dim3(256), 0, s, t, g, f, fscale, M, L, V, G);
+    hipLaunchKernelGGL((leaf_split_kernel<3, 64>), grid, dim3(256), 0, s, t, g, f, fscale, M, L, V, G);
   } else {
-    hipLaunchKernelGGL((leaf_split_kernel<4, 64>), dim3(bx, 3, nrhs), dim3(256), 0, s, t, g, f, fscale, M, L, V, G);
+    hipLaunchKernelGGL((leaf_split_kernel<4, 64>), grid, dim3(256), 0, s, t, g, f, fscale, M, L, V, G);
   }
 }
 
