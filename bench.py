@@ -96,7 +96,7 @@ def main():
     t_inputs = time.perf_counter() - t0
     log(f"inputs: {args.workload}: {tree.n_leaves} leaves, {f_host.size} points, {t_inputs:.1f} s")
 
-    flags = B.BX_FP64 if args.precision == "fp64" else B.BX_SPLIT_BF16
+    flags = B.BX_FP64 if args.precision == "fp64" else B.BX_SPLIT_INT8
     t0 = time.perf_counter()
     ctx = B.Context(args.n, args.p, flags)
     t_tables = time.perf_counter() - t0
@@ -158,7 +158,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "bf16-split+f64",
+        "dtype": "f64" if args.precision == "fp64" else "i8-split+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "precision": args.precision, "n_leaves": tree.n_leaves, "points": npts, "nodes": args.n,
                    "order": args.p, "levels": int(tr.query("n_levels")), "tree_upload_ms": tr.query("upload_ms"),

@@ -64,7 +64,7 @@ enum {
 /* Precision of the near-field table products. */
 enum {
   BX_FP64 = 0,              /* FP64 MFMA throughout */
-  BX_SPLIT_BF16 = 1,        /* near tables as exact BF16 slice products with FP32 accumulation,
+  BX_SPLIT_INT8 = 1,        /* near tables as exact int8 slice products with int32 accumulation,
                                recombined in FP64 (far field, log terms and sums stay FP64) */
   BX_HOST_ONLY = 0x100      /* or-ed in: no device is touched; tables and trees are built on the
                                host for inspection only and evaluation returns BX_E_UNSUPPORTED */
@@ -74,7 +74,7 @@ enum {
  * Create a context on the current HIP device.
  *   n_nodes: collocation nodes per side, one of 4, 8, 16.
  *   p_exp:   expansion order p (coefficients 0..p), 8 <= p <= 47.
- *   flags:   BX_FP64 or BX_SPLIT_BF16, optionally or-ed with BX_HOST_ONLY.
+ *   flags:   BX_FP64 or BX_SPLIT_INT8, optionally or-ed with BX_HOST_ONLY.
  * Errors: BX_E_ARG (out NULL), BX_E_UNSUPPORTED, BX_E_HIP.
  */
 int bx_create(bx_ctx **out, int n_nodes, int p_exp, uint32_t flags);
@@ -134,7 +134,7 @@ enum {
   BX_Q_NEAR_TILES = 11,      /* 16-target tiles of the near kernel */
   BX_Q_NEAR_SLOTS = 12,      /* (tile, configuration) slots of the near kernel */
   BX_Q_UPLOAD_MS = 13,       /* host time of the last bx_tree_upload, milliseconds */
-  BX_Q_SPLIT_PRODUCTS = 14,  /* split contexts: mean BF16 slice products per near table, over leaves */
+  BX_Q_SPLIT_PRODUCTS = 14,  /* split contexts: mean int8 slice products per near table entry, over leaves */
   /* algorithmic FP64 flops of one evaluation phase, one RHS: add the phase index */
   BX_Q_PHASE_FLOPS = 20,
   /* algorithmic bytes of one evaluation phase (each operand read and each result
@@ -174,16 +174,22 @@ int bx_tree_list(const bx_tree *tree, int kind, int64_t *out, int64_t cap, int64
  * [4][p+1][p+1][2], 4 M2L core [KP][KP], 5 M2L source powers [49][KP][2],
  * 6 M2L target powers [49][KP][2], 7 log|d| [49], 8 L2T [3P][2 KP],
  * 9 M2T [20][3P][2 KP], 10 P2L [20][2 KP][P], 11 unit-box weights [P];
- * KP = p+1 rounded up to 16.  With out == NULL only *count is written.
+ * KP = p+1 rounded up to 16.  Split contexts also: 12 int8 slices of the near
+ * tables [33][8][3P][P] (slice a of row r: T[r][k] ~ scale_r sum_a s_a
+ * 2^-7(a+1)), 13 row scales [3P], 14 slice error bounds [2][9] (V rows, then
+ * gradient rows; entry s: bound with s slices for samples |f| < 1).  With
+ * out == NULL only *count is written.
  */
 int bx_table_copy(const bx_ctx *ctx, int which, double *out, int64_t cap, int64_t *count);
 
 /*
- * Split contexts: tolerance of the BF16 slicing of the near tables.  The slice
- * count of each level is the smallest with a truncation bound below
- * tol * ||f||_inf * W^2 for V and tol * ||f||_inf * W for grad V (W = root
- * width; V rows and gradient rows have their own counts), at most 6 slices
- * (48 bits).  Takes effect for trees uploaded after the call; default 1e-11.
+ * Split contexts: tolerance of the int8 slicing of the near tables.  The slice
+ * count of each level (V rows and gradient rows separately) is the smallest
+ * whose rigorous error bound (table and sample residuals and dropped slice
+ * pairs, summed over all 33 configurations) is below tol * ||f||_inf * W^2 for
+ * V and tol * ||f||_inf * W for grad V (W = root width).  Levels that would
+ * need more than 6 slices (42 bits) evaluate their near field in FP64.  Takes
+ * effect for trees uploaded after the call; default 1e-11.
  * Errors: BX_E_ARG.
  */
 int bx_split_tolerance(bx_ctx *ctx, double tol);

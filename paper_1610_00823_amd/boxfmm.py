@@ -18,12 +18,13 @@ LIB_PATH = os.environ.get("BOXFMM_LIB") or os.path.join(HERE, "libboxfmm.so")
 BX_OK = 0
 BX_E_ARG, BX_E_NOT_BALANCED, BX_E_INVALID_TREE, BX_E_UNSUPPORTED, BX_E_HIP, BX_E_OOM, BX_E_NO_TABLES = (
     -1, -2, -3, -4, -5, -6, -7)
-BX_FP64, BX_SPLIT_BF16, BX_HOST_ONLY = 0, 1, 0x100
+BX_FP64, BX_SPLIT_INT8, BX_HOST_ONLY = 0, 1, 0x100
 Q = dict(n_leaves=0, n_boxes=1, n_levels=2, nodes=3, order=4, near_pairs=5, v_pairs=6, w_pairs=7,
          x_pairs=8, near_flops=9, far_flops=10, near_tiles=11, near_slots=12, upload_ms=13,
          split_products=14)
 TABLES = dict(near=0, p2m=1, m2m=2, l2l=3, m2l_core=4, m2l_src_pow=5, m2l_tgt_pow=6, logd=7, l2t=8,
-              m2t=9, p2l=10, weights=11)
+              m2t=9, p2l=10, weights=11, split_slices=12, split_row_scale=13,
+              split_err=14)
 PHASES = ["p2m", "m2m", "m2l", "p2l", "l2l", "leaf"]
 SYMBOLS = ["bx_create", "bx_build_tables", "bx_tree_upload", "bx_volume_eval_grad", "bx_volume_eval",
            "bx_volume_grad", "bx_query", "bx_tree_list", "bx_table_copy", "bx_split_tolerance", "bx_profile",

@@ -45,7 +45,10 @@ struct bx_tree {
   std::vector<void *> dev;
   bx::DevTree dg{};
   double *M = nullptr, *L = nullptr;   // expansions, grown with n_rhs
-  double *fscale = nullptr;            // split contexts: per-leaf sample scales [n_rhs][N_L]
+  // split contexts: per-RHS sample scales, partial maxima, int8 sample slices, per-leaf masses
+  double *fscale = nullptr, *fpart = nullptr, *lmass = nullptr;
+  int8_t *fsl = nullptr;
+  int split_sf = 1;
   int exp_rhs = 0;
   double upload_ms = 0.0;
   int64_t n_slots = 0;
@@ -119,8 +122,8 @@ int bx_create(bx_ctx **out, int n_nodes, int p_exp, uint32_t flags) {
   if (n_nodes != 4 && n_nodes != 8 && n_nodes != 16) return fail(BX_E_UNSUPPORTED, "bx_create: n must be 4, 8 or 16");
   if (p_exp < 8 || p_exp > 47) return fail(BX_E_UNSUPPORTED, "bx_create: p must be in 8..47");
   uint32_t prec = flags & ~(uint32_t)BX_HOST_ONLY;
-  if (prec != BX_FP64 && prec != BX_SPLIT_BF16) return fail(BX_E_UNSUPPORTED, "bx_create: unknown flags");
-  if (prec == BX_SPLIT_BF16 && n_nodes == 4)
+  if (prec != BX_FP64 && prec != BX_SPLIT_INT8) return fail(BX_E_UNSUPPORTED, "bx_create: unknown flags");
+  if (prec == BX_SPLIT_INT8 && n_nodes == 4)
     return fail(BX_E_UNSUPPORTED, "bx_create: split near tables need n = 8 or 16");
   int dev = 0;
   if (!(flags & BX_HOST_ONLY)) {
@@ -160,7 +163,7 @@ int bx_build_tables(bx_ctx *ctx, double quad_tol, const char *cache_dir) {
     if (rc) return fail(rc, "bx_build_tables: table construction failed");
     if (!path.empty()) save_tables(T, path);   // a failed cache write is not an error
   }
-  if (ctx->flags & BX_SPLIT_BF16) build_split_tables(T, ctx->split);
+  if (ctx->flags & BX_SPLIT_INT8) build_split_tables(T, ctx->split);
   if (ctx->flags & BX_HOST_ONLY) {
     ctx->ready = true;
     return BX_OK;
@@ -190,10 +193,13 @@ int bx_build_tables(bx_ctx *ctx, double quad_tol, const char *cache_dir) {
       (rc = upload(ctx->dev, mf, &d.m2m_frag, s)) || (rc = upload(ctx->dev, llf, &d.l2l_frag, s)) ||
       (rc = upload(ctx->dev, xf, &d.p2l_frag, s)))
     return rc;
-  d.near_bf16 = nullptr;
-  d.split_scale_v = ctx->split.scale_v;
-  d.split_scale_d = ctx->split.scale_d;
-  if ((ctx->flags & BX_SPLIT_BF16) && (rc = upload(ctx->dev, ctx->split.a, &d.near_bf16, s))) return rc;
+  d.near_i8 = nullptr;
+  d.split_row_scale = d.split_cfg_w2 = nullptr;
+  if ((ctx->flags & BX_SPLIT_INT8) &&
+      ((rc = upload(ctx->dev, ctx->split.a, &d.near_i8, s)) ||
+       (rc = upload(ctx->dev, ctx->split.row_scale, &d.split_row_scale, s)) ||
+       (rc = upload(ctx->dev, ctx->split.cfg_w2, &d.split_cfg_w2, s))))
+    return rc;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "bx_build_tables: upload");
   ctx->ready = true;
@@ -202,46 +208,28 @@ int bx_build_tables(bx_ctx *ctx, double quad_tol, const char *cache_dir) {
 
 namespace bx {
 namespace {
-// Work units of the leaf kernels, in launch order: (tile, first row tile | row
-// tiles per wave << 16), tile -1 for an empty block.  A unit costs about its
-// slot count times its rows.  Tiles far above the balanced share of one resident
-// block are split by rows (one row tile per wave), so that no single tile sets
-// the kernel's duration.  Each XCD (blocks are dealt to the 8 XCDs round-robin)
-// receives a contiguous range of tiles of equal total cost, for the L2 locality
-// of the operator tables, in decreasing unit cost: the dispatcher then runs
-// longest-first.
-void leaf_units(const std::vector<int> &tile_ptr, int n, int blocks_per_cu, int n_cu, std::vector<int> &unit_tile,
-                std::vector<int> &unit_mt) {
-  const int P = n * n, MTR = std::max(1, 3 * P / 16);
-  const int TPW = n == 4 ? 1 : (n == 8 ? 3 : 4), G = (MTR + 4 * TPW - 1) / (4 * TPW);
-  const int ntiles = (int)tile_ptr.size() - 1;
-  struct U { int tile, mt; double cost; };
-  auto cost_of = [](int slots, int ni) { return slots * (ni + 0.35); };
-  double total = 0;
-  for (int tt = 0; tt < ntiles; ++tt) total += G * cost_of(tile_ptr[tt + 1] - tile_ptr[tt], TPW);
-  const double share = total / std::max(1, blocks_per_cu * n_cu);
-  std::vector<U> units;
-  for (int tt = 0; tt < ntiles; ++tt) {
-    const int ns = tile_ptr[tt + 1] - tile_ptr[tt];
-    const bool heavy = TPW > 1 && cost_of(ns, TPW) > 1.25 * share;
-    for (int gg = 0; gg < G; ++gg) {
-      if (!heavy) units.push_back({tt, gg * 4 * TPW | TPW << 16, cost_of(ns, TPW)});
-      else
-        for (int j = 0; j < TPW; ++j) units.push_back({tt, (gg * 4 * TPW + 4 * j) | 1 << 16, cost_of(ns, 1)});
-    }
-  }
+struct Unit {
+  int tile, mt;
+  double cost;
+};
+
+// Launch order of work units: each XCD (blocks are dealt to the 8 XCDs
+// round-robin) receives a contiguous range of units of equal total cost, for
+// the L2 locality of the operator tables, in decreasing cost, so that the
+// dispatcher runs longest-first.  Padding blocks get tile -1.
+void order_units(const std::vector<Unit> &units, std::vector<int> &unit_tile, std::vector<int> &unit_mt) {
   double sum = 0;
-  for (const U &u : units) sum += u.cost;
-  std::vector<std::vector<U>> part(8);
+  for (const Unit &u : units) sum += u.cost;
+  std::vector<std::vector<Unit>> part(8);
   double run = 0;
-  for (const U &u : units) {
+  for (const Unit &u : units) {
     const int x = std::min(7, (int)(8.0 * run / std::max(sum, 1e-300)));
     part[x].push_back(u);
     run += u.cost;
   }
   size_t per = 0;
   for (auto &v : part) {
-    std::stable_sort(v.begin(), v.end(), [](const U &a, const U &b) { return a.cost > b.cost; });
+    std::stable_sort(v.begin(), v.end(), [](const Unit &a, const Unit &b) { return a.cost > b.cost; });
     per = std::max(per, v.size());
   }
   unit_tile.assign(8 * per, -1);
@@ -251,6 +239,33 @@ void leaf_units(const std::vector<int> &tile_ptr, int n, int blocks_per_cu, int 
       unit_tile[8 * j + x] = part[x][j].tile;
       unit_mt[8 * j + x] = part[x][j].mt;
     }
+}
+
+// Work units of the FP64 leaf kernel: (tile, first row tile | row tiles per
+// wave << 16).  A unit costs about its slot count times its rows; tiles far
+// above the balanced share of one resident block are split by rows (one row
+// tile per wave), so that no single tile sets the kernel's duration.
+void leaf_units(const std::vector<int> &tile_ptr, int n, int blocks_per_cu, int n_cu, std::vector<int> &unit_tile,
+                std::vector<int> &unit_mt) {
+  const int P = n * n, MTR = std::max(1, 3 * P / 16);
+  const int TPW = n == 4 ? 1 : (n == 8 ? 3 : 4), G = (MTR + 4 * TPW - 1) / (4 * TPW);
+  const int ntiles = (int)tile_ptr.size() - 1;
+  auto cost_of = [](int slots, int ni) { return slots * (ni + 0.35); };
+  double total = 0;
+  for (int tt = 0; tt < ntiles; ++tt) total += G * cost_of(tile_ptr[tt + 1] - tile_ptr[tt], TPW);
+  const double share = total / std::max(1, blocks_per_cu * n_cu);
+  std::vector<Unit> units;
+  for (int tt = 0; tt < ntiles; ++tt) {
+    const int ns = tile_ptr[tt + 1] - tile_ptr[tt];
+    if (ns == 0) continue;
+    const bool heavy = TPW > 1 && cost_of(ns, TPW) > 1.25 * share;
+    for (int gg = 0; gg < G; ++gg) {
+      if (!heavy) units.push_back({tt, gg * 4 * TPW | TPW << 16, cost_of(ns, TPW)});
+      else
+        for (int j = 0; j < TPW; ++j) units.push_back({tt, (gg * 4 * TPW + 4 * j) | 1 << 16, cost_of(ns, 1)});
+    }
+  }
+  order_units(units, unit_tile, unit_mt);
 }
 }  // namespace
 }  // namespace bx
@@ -293,7 +308,7 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
   std::vector<int> order(H.n_leaves);
   for (int i = 0; i < H.n_leaves; ++i) order[i] = i;
   // split contexts: tiles hold one level (the slice count depends on it)
-  const bool split = (ctx->flags & BX_SPLIT_BF16) != 0;
+  const bool split = (ctx->flags & BX_SPLIT_INT8) != 0;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     if (split && leaf_level[a] != leaf_level[b]) return leaf_level[a] > leaf_level[b];
     return sig[a] < sig[b];
@@ -307,7 +322,8 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
   }
   int ntiles = (int)tile_first.size();
   tile_first.push_back(H.n_leaves);
-  std::vector<int> tile_nsl(ntiles, 0);
+  std::vector<int> tile_nsl(ntiles, 0), nslot_ptr(ntiles + 1, 0), nslot_cfg, nslot_src;
+  int split_sf = 1;
   std::vector<int> tile_tgt((size_t)ntiles * TL, -1), tile_ptr(ntiles + 1, 0), slot_aoff, slot_type, slot_src,
       slot_op;
   for (int tt = 0; tt < ntiles; ++tt) {
@@ -317,24 +333,34 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       tile_tgt[(size_t)tt * TL + k] = leaf;
       uni |= sig[leaf];
     }
+    bool near_i8 = false;
     if (split) {   // slices of the V rows (low byte) and of the gradient rows (next byte)
       const int lv = leaf_level[order[tile_first[tt]]];
-      tile_nsl[tt] = split_slices(ctx->split, lv, ctx->split_tol, false) |
-                     split_slices(ctx->split, lv, ctx->split_tol, true) << 8;
+      const int sv = split_slices(ctx->split, lv, ctx->split_tol, false),
+                sd = split_slices(ctx->split, lv, ctx->split_tol, true);
+      near_i8 = sv > 0 && sd > 0;   // otherwise more slices than the int8 kernel keeps: FP64
+      tile_nsl[tt] = near_i8 ? sv | sd << 8 : 0;
+      if (near_i8) split_sf = std::max(split_sf, std::max(sv, sd));
     }
     for (int c = 0; c < NCFG_U; ++c) {
       if (!(uni >> c & 1)) continue;
-      slot_aoff.push_back((int)(FL.near0 + c * FL.near_step));
-      slot_type.push_back(0);
-      slot_op.push_back(c);
+      if (near_i8) {
+        nslot_cfg.push_back(c);
+      } else {
+        slot_aoff.push_back((int)(FL.near0 + c * FL.near_step));
+        slot_type.push_back(0);
+        slot_op.push_back(c);
+      }
+      std::vector<int> &dst = near_i8 ? nslot_src : slot_src;
       for (int k = 0; k < TL; ++k) {
         int leaf = tile_tgt[(size_t)tt * TL + k], src = -1;
         if (leaf >= 0)
           for (int e = up[leaf]; e < up[leaf + 1]; ++e)
             if (uc[e] == c) src = us[e];
-        slot_src.push_back(src);
+        dst.push_back(src);
       }
     }
+    nslot_ptr[tt + 1] = (int)nslot_cfg.size();
     slot_aoff.push_back((int)FL.l2t);
     slot_type.push_back(1);
     slot_op.push_back(NCFG_U);
@@ -358,9 +384,23 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
     tile_ptr[tt + 1] = (int)slot_type.size();
   }
   g.n_tiles = ntiles;
-  std::vector<int> unit_tile, unit_mt;
-  leaf_units(tile_ptr, ctx->n, split ? 1 : 2, ctx->n_cu, unit_tile, unit_mt);
+  std::vector<int> unit_tile, unit_mt, nunit_tile, nunit_mt;
+  leaf_units(tile_ptr, ctx->n, 2, ctx->n_cu, unit_tile, unit_mt);
   g.n_units = (int)unit_tile.size();
+  if (split) {   // int8 near kernel: every tile (it writes V and G), 12 row tiles per block
+    const int MTR = 3 * ctx->n * ctx->n / 16;
+    std::vector<Unit> nu;
+    for (int tt = 0; tt < ntiles; ++tt) {
+      const int sv = tile_nsl[tt] & 255, sd = tile_nsl[tt] >> 8;
+      const double pairs = (sv * (sv + 1) / 2.0 + 2.0 * sd * (sd + 1) / 2.0) / 3.0;
+      for (int mt0 = 0; mt0 < MTR; mt0 += 12)
+        nu.push_back({tt, mt0, 1.0 + (nslot_ptr[tt + 1] - nslot_ptr[tt]) * pairs});
+    }
+    order_units(nu, nunit_tile, nunit_mt);
+  }
+  g.n_nunits = (int)nunit_tile.size();
+  g.split_sf = split_sf;
+  t->split_sf = split_sf;
   // X-list tiles: target boxes with X entries, sorted by configuration set
   std::vector<int> xb;
   std::vector<uint32_t> xsig(H.n_boxes, 0);
@@ -423,7 +463,11 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       (rc = upload(t->dev, slot_aoff, &g.slot_aoff, s)) || (rc = upload(t->dev, slot_type, &g.slot_type, s)) ||
       (rc = upload(t->dev, slot_op, &g.slot_op, s)) || (rc = upload(t->dev, tile_nsl, &g.tile_nsl, s)) ||
       (rc = upload(t->dev, slot_src, &g.slot_src, s)) || (rc = upload(t->dev, unit_tile, &g.unit_tile, s)) ||
-      (rc = upload(t->dev, unit_mt, &g.unit_mt, s))) {
+      (rc = upload(t->dev, unit_mt, &g.unit_mt, s)) ||
+      (split && ((rc = upload(t->dev, nslot_ptr, &g.nslot_ptr, s)) || (rc = upload(t->dev, nslot_cfg, &g.nslot_cfg, s)) ||
+                 (rc = upload(t->dev, nslot_src, &g.nslot_src, s)) ||
+                 (rc = upload(t->dev, nunit_tile, &g.nunit_tile, s)) ||
+                 (rc = upload(t->dev, nunit_mt, &g.nunit_mt, s))))) {
     bx_tree_destroy(t);
     return rc;
   }
@@ -445,6 +489,15 @@ static void drop_graphs(bx_tree *t) {
   }
 }
 
+static void free_split_buffers(bx_tree *t) {
+  if (t->fscale) (void)hipFree(t->fscale);
+  if (t->fpart) (void)hipFree(t->fpart);
+  if (t->lmass) (void)hipFree(t->lmass);
+  if (t->fsl) (void)hipFree(t->fsl);
+  t->fscale = t->fpart = t->lmass = nullptr;
+  t->fsl = nullptr;
+}
+
 static int ensure_expansions(bx_tree *t, int nrhs) {
   if (t->exp_rhs >= nrhs) return BX_OK;
   drop_graphs(t);
@@ -453,11 +506,16 @@ static int ensure_expansions(bx_tree *t, int nrhs) {
   t->M = t->L = nullptr;
   t->exp_rhs = 0;
   size_t bytes = (size_t)nrhs * t->H.n_boxes * t->ctx->T.KP * 2 * sizeof(double);
-  if (t->fscale) (void)hipFree(t->fscale);
-  t->fscale = nullptr;
+  free_split_buffers(t);
   hipError_t e = hipMalloc((void **)&t->M, bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&t->L, bytes);
-  if (e == hipSuccess) e = hipMalloc((void **)&t->fscale, (size_t)nrhs * t->H.n_leaves * sizeof(double));
+  if (e == hipSuccess && (t->ctx->flags & BX_SPLIT_INT8)) {
+    const size_t NL = t->H.n_leaves, P = t->ctx->T.P;
+    e = hipMalloc((void **)&t->fscale, (size_t)nrhs * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&t->fpart, (size_t)nrhs * 512 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&t->lmass, (size_t)nrhs * NL * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&t->fsl, (size_t)nrhs * t->split_sf * NL * P);
+  }
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(BX_E_OOM, "expansion buffers") : hip_fail(e, "hipMalloc");
   t->exp_rhs = nrhs;
   return BX_OK;
@@ -498,8 +556,13 @@ static int enqueue_eval(bx_ctx *ctx, bx_tree *t, const double *f, int nrhs, doub
   for (int l = 0; l + 1 < H.n_levels; ++l)
     launch_l2l(d, g, t->int_boxes + t->int_start[l], t->int_start[l + 1] - t->int_start[l], nrhs, t->L, s);
   if ((rc = mark(BX_PH_L2L, false)) || (rc = mark(BX_PH_LEAF, true))) return rc;
-  if (ctx->flags & BX_SPLIT_BF16) launch_leaf_split(d, g, f, t->fscale, nrhs, t->M, t->L, V, G, s);
-  else launch_leaf(d, g, f, nrhs, t->M, t->L, V, G, s);
+  if (ctx->flags & BX_SPLIT_INT8) {
+    launch_split_prep(d, g, f, nrhs, t->fpart, t->fscale, t->fsl, t->lmass, s);
+    launch_leaf_near_i8(d, g, t->fsl, t->lmass, t->fscale, nrhs, V, G, s);
+    launch_leaf(d, g, f, nrhs, t->M, t->L, V, G, true, s);
+  } else {
+    launch_leaf(d, g, f, nrhs, t->M, t->L, V, G, false, s);
+  }
   if ((rc = mark(BX_PH_LEAF, false))) return rc;
   if (ctx->profiling) ctx->ev_evals++;
   hipError_t e = hipGetLastError();
@@ -673,13 +736,14 @@ int bx_query(const bx_ctx *ctx, const bx_tree *tree, int what, double *out) {
     case BX_Q_NEAR_TILES: *out = tree->dg.n_tiles; break;
     case BX_Q_NEAR_SLOTS: *out = (double)tree->n_slots; break;
     case BX_Q_UPLOAD_MS: *out = tree->upload_ms; break;
-    case BX_Q_SPLIT_PRODUCTS: {   // BF16 slice products per near (target, source) pair, averaged over pairs
-      if (!(ctx->flags & BX_SPLIT_BF16)) { *out = 0; break; }
+    case BX_Q_SPLIT_PRODUCTS: {   // int8 slice products per near table entry, averaged over leaves
+      if (!(ctx->flags & BX_SPLIT_INT8)) { *out = 0; break; }
       double num = 0, den = 0;
       for (int i = 0; i < H.n_leaves; ++i) {
         int sv = split_slices(ctx->split, H.lvl[H.box_of_leaf[i]], ctx->split_tol, false);
         int sd = split_slices(ctx->split, H.lvl[H.box_of_leaf[i]], ctx->split_tol, true);
-        num += (sv * (sv + 1) / 2.0 + 2.0 * sd * (sd + 1) / 2.0) / 3.0;   // V rows : gradient rows = 1 : 2
+        if (sv > 0 && sd > 0)   // V rows : gradient rows = 1 : 2; leaves left in FP64 count 0
+          num += (sv * (sv + 1) / 2.0 + 2.0 * sd * (sd + 1) / 2.0) / 3.0;
         den += 1;
       }
       *out = den > 0 ? num / den : 0;
@@ -707,6 +771,31 @@ int bx_table_copy(const bx_ctx *ctx, int which, double *out, int64_t cap, int64_
   const Tables &T = ctx->T;
   const std::vector<double> *v[12] = {&T.near_, &T.p2m, &T.m2m, &T.l2l, &T.H, &T.pw_src,
                                       &T.pw_tgt, &T.logd, &T.l2t, &T.m2t, &T.p2l, &T.wq};
+  if (which >= 12 && which <= 14) {   // split tables, as doubles
+    if (!(ctx->flags & BX_SPLIT_INT8)) return fail(BX_E_ARG, "bx_table_copy: not a split context");
+    const SplitTables &S = ctx->split;
+    std::vector<double> tmp;
+    if (which == 12) {   // slices [33][SMAX][3P][P] in natural order
+      const int P = T.P, R = 3 * P, MTR = R / 16, NCH = P / 64;
+      tmp.resize((size_t)NCFG_U * SPLIT_SMAX * R * P);
+      for (int c = 0; c < NCFG_U; ++c)
+        for (int a = 0; a < SPLIT_SMAX; ++a)
+          for (int r = 0; r < R; ++r)
+            for (int k = 0; k < P; ++k) {
+              const int mt = r / 16, lane = r % 16 + 16 * (k % 64 / 16), ch = k / 64;
+              tmp[(((size_t)c * SPLIT_SMAX + a) * R + r) * P + k] =
+                  S.a[(((((size_t)c * SPLIT_SMAX + a) * MTR + mt) * NCH + ch) * 64 + lane) * 16 + k % 16];
+            }
+    } else if (which == 13) {
+      tmp = S.row_scale;
+    } else {
+      tmp = S.err_v;
+      tmp.insert(tmp.end(), S.err_d.begin(), S.err_d.end());
+    }
+    *count = (int64_t)tmp.size();
+    if (out) std::memcpy(out, tmp.data(), (size_t)std::min<int64_t>(cap, *count) * sizeof(double));
+    return BX_OK;
+  }
   if (which < 0 || which >= 12) return fail(BX_E_ARG, "bx_table_copy: unknown table");
   *count = (int64_t)v[which]->size();
   if (out) std::memcpy(out, v[which]->data(), (size_t)std::min<int64_t>(cap, *count) * sizeof(double));
@@ -743,7 +832,7 @@ void bx_tree_destroy(bx_tree *tree) {
   for (void *p : tree->dev) (void)hipFree(p);
   if (tree->M) (void)hipFree(tree->M);
   if (tree->L) (void)hipFree(tree->L);
-  if (tree->fscale) (void)hipFree(tree->fscale);
+  free_split_buffers(tree);
   delete tree;
 }
 

@@ -58,22 +58,25 @@ struct LeafFragLayout {
 LeafFragLayout leaf_frag_layout(int n, int p);
 void build_leaf_frag(const Tables &T, std::vector<double> &out, std::vector<double> &mass);
 
-// Split (BF16-slice) form of the near tables.  Each table row type (V rows,
-// gradient rows) shares one power-of-two scale 2^E; a value x is written as
-// sum_a s_a 2^(E - 8(a+1)) with integers |s_a| <= 256 taken by truncation; each
-// slice is stored with its scale (exact in BF16).  Fragments for
-// v_mfma_f32_16x16x32_bf16:
-// a[(((((c * SMAX + a) * MTR + mt) * NC + chunk) * 2 + step) * 64 + lane) * 8 + e]
-//   = slice a of A[mt*16 + lane%16][chunk*KC + step*32 + (lane/16)*8 + e] (bits of a BF16).
-constexpr int SPLIT_SMAX = 6;
+// Split (int8-slice) form of the near tables.  Row r of every near table has
+// one power-of-two scale 2^E_r (max |T[r][k]| over configurations and k is at
+// most 2^E_r 127.5/128); a value is x = 2^E_r sum_a t_a 2^-7(a+1) + residual
+// with integer slices t_a rounded to nearest (|t_0| <= 127, |t_a| <= 64 after).
+// Fragments for v_mfma_i32_16x16x64_i8 (16 bytes per lane):
+// a[((((c * SMAX + a) * MTR + mt) * NCH + ch) * 64 + lane) * 16 + e]
+//   = slice a of T_c[mt*16 + lane%16][ch*64 + (lane/16)*16 + e],  MTR = 3P/16, NCH = P/64.
+constexpr int SPLIT_SMAX = 8;   // table slices stored
+constexpr int SPLIT_SG = 6;     // slice count the int8 kernel handles; tiles needing more stay FP64
 struct SplitTables {
-  std::vector<uint16_t> a;
-  double scale_v = 1.0, scale_d = 1.0;   // 2^E of the V rows and of the gradient rows
-  double bound_v = 0.0, bound_d = 0.0;   // max over rows of sum over configs and k of 2^E (error bound factor)
+  std::vector<int8_t> a;
+  std::vector<double> row_scale;      // [3P] 2^E_r
+  std::vector<double> err_v, err_d;   // [SMAX + 1]: error bound with s slices for samples |f| < 1, per row type
+  std::vector<double> cfg_w2;         // [33] mass weight factor (source width / target width)^2
 };
 void build_split_tables(const Tables &T, SplitTables &S);
-// Slices needed at level l so that the slice truncation stays below tol times
-// ||f||_inf W^2 (V) and ||f||_inf W (gradient), W the root width.
+// Slices needed at level l so that the slice error stays below tol times
+// ||f||_inf W^2 (values) or ||f||_inf W (gradients), W the root width; 0 when
+// more than SPLIT_SG would be needed.
 int split_slices(const SplitTables &S, int level, double tol, bool grad_rows);
 void build_p2m_frag(const Tables &T, std::vector<double> &out);
 // M2M 4 x [2KP][2KP], L2L 4 x [2KP][2KP] on interleaved coefficients, and the

@@ -15,9 +15,10 @@ struct DevTables {
   const double *leaf_frag, *p2m_frag;
   const double *leaf_mass;   // [54][KMAX] mass-row weights of the leaf operators
   int leaf_kmax;
-  // split (BF16-slice) near tables and their row-type scales (split contexts only)
-  const uint16_t *near_bf16;
-  double split_scale_v, split_scale_d;
+  // split contexts: int8 slices of the near tables (layout in bx_internal.h),
+  // the per-row scales 2^E_r [3P] and the mass factors w_c^2 of the 33 configurations
+  const int8_t *near_i8;
+  const double *split_row_scale, *split_cfg_w2;
   // M2M 4 x [2KP][2KP] and L2L 4 x [2KP][2KP] on interleaved coefficients, and
   // P2L per X configuration [2KP + mass row, padded][P], all fragment-major.
   const double *m2m_frag, *l2l_frag, *p2l_frag;
@@ -57,11 +58,20 @@ struct DevTree {
   const int *slot_type;    // [n_slots] 0: samples f of a source leaf (K = P); 1: local expansion
                            // of the target's box; 2: multipole of a source box (K = 2 KP)
   const int *slot_src;     // [n_slots][64] leaf or box index, -1 = none
-  const int *tile_nsl;     // [n_tiles] BF16 slices of the near tables (split contexts; tiles of one level)
+  const int *tile_nsl;     // [n_tiles] split contexts: slices of the V rows | gradient rows << 8 (tiles of one
+                           // level); 0 for a tile whose near field runs in FP64
   // work units of the leaf kernels in launch order (one block each): tile (-1 =
   // empty block) and first row tile | (row tiles per wave) << 16
   int n_units;
   const int *unit_tile, *unit_mt;
+  // split contexts: the U slots of each tile for the int8 kernel (the FP64 slots
+  // above then hold L2T, the W list and the U slots of tiles left in FP64), its
+  // work units (tile, first row tile) and the number of sample slices
+  const int *nslot_ptr;    // [n_tiles + 1]
+  const int *nslot_cfg;    // [n_nslots]
+  const int *nslot_src;    // [n_nslots][64] source leaf, -1 = none
+  int n_nunits, split_sf;
+  const int *nunit_tile, *nunit_mt;
 };
 
 // Expansion storage: [n_rhs][NB][KP] complex (interleaved re, im).
@@ -74,12 +84,17 @@ void launch_p2l(const DevTables &t, const DevTree &g, const double *f, int nrhs,
 // Downward pass step from the internal boxes `boxes` of one level to their children.
 void launch_l2l(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *L,
                 hipStream_t s);
-// Near tables + L2T + W list for every leaf: writes V and G.
+// Near tables + L2T + W list for every leaf (the slots of the tree's tiles):
+// writes V and G, or adds to them when accumulate is set.
 void launch_leaf(const DevTables &t, const DevTree &g, const double *f, int nrhs, const double *M,
-                 const double *L, double *V, double *G, hipStream_t s);
-// Split-precision variant: near tables as exact BF16 slice products; fscale
-// [n_rhs][N_L] receives each leaf's power-of-two scale (>= max |f|).
-void launch_leaf_split(const DevTables &t, const DevTree &g, const double *f, double *fscale, int nrhs,
-                       const double *M, const double *L, double *V, double *G, hipStream_t s);
+                 const double *L, double *V, double *G, bool accumulate, hipStream_t s);
+// Split precision: per-RHS sample scale fscale [n_rhs], int8 sample slices fsl
+// [n_rhs][split_sf][N_L][P] and per-leaf masses lmass [n_rhs][N_L]; fpart holds
+// [n_rhs][512] partial maxima.
+void launch_split_prep(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *fpart,
+                       double *fscale, int8_t *fsl, double *lmass, hipStream_t s);
+// Int8 near field of every tile: writes V and G (then launch_leaf accumulates the rest).
+void launch_leaf_near_i8(const DevTables &t, const DevTree &g, const int8_t *fsl, const double *lmass,
+                         const double *fscale, int nrhs, double *V, double *G, hipStream_t s);
 
 }  // namespace bx

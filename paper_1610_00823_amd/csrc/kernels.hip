@@ -7,6 +7,8 @@
 // level, and they are applied here in FP64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace bx {
@@ -348,7 +350,7 @@ template <int TPW, int KC>
 __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree g, const double *__restrict__ f,
                                                            const double *__restrict__ M,
                                                            const double *__restrict__ L, double *__restrict__ V,
-                                                           double *__restrict__ G) {
+                                                           double *__restrict__ G, int accumulate) {
   constexpr int KSC = KC / 4, PERT = KC / 4, SB = KC + 1;
   __shared__ double sB[2][LEAF_TILE * SB];
   __shared__ double sMass[LEAF_TILE];
@@ -476,244 +478,241 @@ __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = mt * 16 + 4 * kq + r;        // the A rows of each tile are permuted to match
-        if (row < P) Vt[row] = h * h * acc[i][nt][r] + lg;
-        else Gt[row - P] = h * acc[i][nt][r];
+        if (row < P) Vt[row] = (accumulate ? Vt[row] : 0.0) + (h * h * acc[i][nt][r] + lg);
+        else Gt[row - P] = (accumulate ? Gt[row - P] : 0.0) + h * acc[i][nt][r];
       }
     }
   }
 }
 
 
-// ------------------------------------------- split-precision leaf evaluation
-// As leaf_mfma_kernel, but the near-table slots run as exact BF16 slice
-// products.  A table value is sum_a t_a 2^(Et - 8(a+1)) and a sample
-// sum_b s_b 2^(Ef - 8(b+1)), integers |t_a|, |s_b| <= 256 stored with their
-// scales (exact in BF16; Et per row type, Ef per source leaf).  Within one slot
-// every product of slice group d = a + b has the same scale, and a 32-term
-// v_mfma_f32_16x16x32_bf16 sum of them is an integer below 2^22 times that
-// scale: exact in FP32 (a group of d+1 pairs over 64 k stays below 2^24 for
-// d <= 3; later groups lie below 2^-24 of the result).  Each group's sum is
-// added to the FP64 accumulator when the group is complete (groups of
-// different scales are never mixed in one FP32 sum: the MFMA accumulation of
-// such mixtures was measured to lose about 2^-33).  S per tile and row type
-// comes from the tile's level.  L2T, W, the mass (log h) term and all scalings stay FP64.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float flt4 __attribute__((ext_vector_type(4)));
+// ------------------------------------------- split-precision near field
+// The near-table products T f run on exact int8 slices.  A table row r is
+// scaled by 2^E_r and the samples of one right-hand side by 2^Ef (max |f| <
+// 2^Ef 127.5/128), each cut into integer slices of 7 bits (rounded to nearest):
+//   T = 2^E_r sum_a t_a 2^-7(a+1),   f = 2^Ef sum_b s_b 2^-7(b+1).
+// The products of slice group d = a + b all carry the scale 2^(E_r+Ef-7(d+2)),
+// so v_mfma_i32_16x16x64_i8 sums them exactly in int32 (|t_a s_b| <= 127^2, 64
+// terms per instruction, at most 6 pairs per group and 48 slots per tile stay
+// below 2^31) across every slot of a tile; groups with a + b >= S are dropped.
+// FP64 is used only to scale and add the S group sums of each output.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
-__device__ inline flt4 mfma_bf16(bf16x8 a, bf16x8 b, flt4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+__device__ inline i32x4 mfma_i8(i32x4 a, i32x4 b, i32x4 c) {
+  return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
 }
 
-// power-of-two scale 2^e >= max |f| of each leaf (1 for an all-zero leaf)
-__global__ void __launch_bounds__(64) leaf_scale_kernel(const double *__restrict__ f, int P, int n_leaves,
-                                                        double *__restrict__ fscale) {
-  const int leaf = blockIdx.x, rhs = blockIdx.y;
-  const double *fl = f + ((size_t)rhs * n_leaves + leaf) * P;
+constexpr int NEAR_SG = 6;      // slice groups of the int8 kernel (tiles needing more stay FP64)
+constexpr int NEAR_SMAX = 8;    // table slices stored
+constexpr int FMAX_BLOCKS = 512;
+
+// max |f| per right-hand side: block partial maxima
+__global__ void __launch_bounds__(256) fmax_partial_kernel(const double *__restrict__ f, size_t count,
+                                                           double *__restrict__ part) {
+  const int rhs = blockIdx.y;
+  const double *fr = f + (size_t)rhs * count;
   double m = 0.0;
-  for (int j = threadIdx.x; j < P; j += 64) m = fmax(m, fabs(fl[j]));
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256)
+    m = fmax(m, fabs(fr[i]));
   for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-  if (threadIdx.x == 0) {
-    int e = 0;
-    frexp(m, &e);
-    fscale[(size_t)rhs * n_leaves + leaf] = m > 0.0 ? ldexp(1.0, e) : 1.0;
+  __shared__ double sm[4];
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)rhs * gridDim.x + blockIdx.x] = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+}
+
+// Sample scale, int8 slices fsl[rhs][b][leaf][k] (b < Sf) and per-leaf masses
+// sum_k wq_k f_k.  Block = 256 threads = 256 / P leaves (P = 64) or one leaf
+// (P = 256); every block reduces the partial maxima itself.
+__global__ void __launch_bounds__(256) split_prep_kernel(const double *__restrict__ f, const double *__restrict__ wq,
+                                                         int P, int n_leaves, const double *__restrict__ part,
+                                                         int nparts, int Sf, double *__restrict__ fscale,
+                                                         int8_t *__restrict__ fsl, double *__restrict__ lmass) {
+  const int rhs = blockIdx.y, tid = threadIdx.x;
+  __shared__ double sm[4];
+  double m = 0.0;
+  for (int i = tid; i < nparts; i += 256) m = fmax(m, part[(size_t)rhs * nparts + i]);
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((tid & 63) == 0) sm[tid >> 6] = m;
+  __syncthreads();
+  m = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+  __syncthreads();
+  int e = 0;
+  const double fr = m > 0.0 ? frexp(m, &e) : 0.0;
+  if (fr * 128.0 >= 127.5) ++e;
+  const double inv = m > 0.0 ? ldexp(1.0, -e) : 0.0;
+  if (blockIdx.x == 0 && tid == 0) fscale[rhs] = m > 0.0 ? ldexp(1.0, e) : 1.0;
+  const int lpb = P >= 256 ? 1 : 256 / P;
+  const int leaf = blockIdx.x * lpb + tid / P, k = tid % P;
+  const bool ok = leaf < n_leaves && tid < lpb * P;
+  double x = 0.0;
+  if (ok) {
+    x = f[((size_t)rhs * n_leaves + leaf) * P + k];
+    double v = x * inv;
+    for (int b = 0; b < Sf; ++b) {
+      const double sc = v * 128.0, t = rint(sc);
+      v = sc - t;
+      fsl[(((size_t)rhs * Sf + b) * n_leaves + leaf) * P + k] = (int8_t)t;
+    }
+  }
+  // per-leaf mass: P = 64 -> one wave per leaf; P = 256 -> four waves
+  double w = ok ? wq[k] * x : 0.0;
+  for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+  if (P <= 64) {
+    if ((tid & 63) == 0 && ok) lmass[(size_t)rhs * n_leaves + leaf] = w;
+  } else {
+    if ((tid & 63) == 0) sm[tid >> 6] = w;
+    __syncthreads();
+    if (tid == 0 && leaf < n_leaves) lmass[(size_t)rhs * n_leaves + leaf] = ((sm[0] + sm[1]) + sm[2]) + sm[3];
   }
 }
 
-__device__ inline uint32_t bf16_bits(double v) { return __float_as_uint((float)v) >> 16; }
-
-template <int TPW, int KC>
-__global__ void __launch_bounds__(256, 1) leaf_split_kernel(DevTables t, DevTree g, const double *__restrict__ f,
-                                                            const double *__restrict__ fscale,
-                                                            const double *__restrict__ M,
-                                                            const double *__restrict__ L, double *__restrict__ V,
-                                                            double *__restrict__ G) {
-  constexpr int SMAX = 6, PERT = KC / 4, SB = KC + 1, SBH = KC + 8, NST = KC / 32, KSC = KC / 4;
-  constexpr int BYTES64 = LEAF_TILE * SB * 8, BYTES16 = SMAX * LEAF_TILE * SBH * 2;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[BYTES64 > BYTES16 ? BYTES64 : BYTES16];
-  __shared__ double sMass[LEAF_TILE];
-  double *sB = (double *)smem;
-  uint16_t *sH = (uint16_t *)smem;
-  const int tile = g.unit_tile[blockIdx.x];
-  if (tile < 0) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
-  const int rhs = blockIdx.z, P = t.P, K2 = 2 * t.KP, MTR = 3 * P / 16, NCU = P / KC;
-  const int mtg = g.unit_mt[blockIdx.x] & 0xffff, ni = g.unit_mt[blockIdx.x] >> 16;
-  const int s0 = g.tile_ptr[tile], s1 = g.tile_ptr[tile + 1];
-  const int nsl_v = g.tile_nsl[tile] & 255, nsl_d = g.tile_nsl[tile] >> 8;
-  const int nsl = nsl_v > nsl_d ? nsl_v : nsl_d;
-  const double *fr = f + (size_t)rhs * g.n_leaves * P;
-  const double *fs = fscale + (size_t)rhs * g.n_leaves;
-  const double *Lr = L + (size_t)rhs * g.n_boxes * K2, *Mr = M + (size_t)rhs * g.n_boxes * K2;
-  const int *slot_type = g.slot_type, *slot_op = g.slot_op, *slot_aoff = g.slot_aoff;
-  const double *leaf_frag = t.leaf_frag, *leaf_mass = t.leaf_mass;
-  const int kmax = t.leaf_kmax;
-  const int scol = threadIdx.x >> 2, sq = threadIdx.x & 3;
-  const int stgt = g.tile_tgt[tile * LEAF_TILE + scol];
-  const double sinv_h2 = stgt >= 0 ? 1.0 / (box_h(g.width, g.leaf_level[stgt]) * box_h(g.width, g.leaf_level[stgt]))
-                                   : 0.0;
-  const int *slot_src = g.slot_src + scol;
-  int tns[TPW];
+// Near (U list) field of one 64-leaf tile in int8 slices; writes V and G (the
+// FP64 leaf kernel then adds L2T and the W list).  Block = 8 waves: wave
+// (w4, half) owns row tiles mt0 + w4 + 4i (i < TPW) and the 16-column tiles
+// 2 half, 2 half + 1.  Per work item (slot, 64-wide K chunk) the B slices of
+// the 64 columns are staged in LDS (double buffered, swizzled so that the
+// 16-lane groups of a 16-byte read hit distinct banks); the A slices stream
+// from the table two iterations ahead, in the slice order 0,5,1,4,2,3 that
+// alternates long and short iterations.
+template <int TPW, int NCH>
+__global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTree g, const int8_t *__restrict__ fsl,
+                                                             const double *__restrict__ lmass,
+                                                             const double *__restrict__ fscale,
+                                                             double *__restrict__ V, double *__restrict__ G) {
+  constexpr int SG = NEAR_SG, P = 64 * NCH, MTR = 3 * P / 16, PPT = SG * 256 / 512;
+  constexpr int SEQ[SG] = {0, 5, 1, 4, 2, 3};
+  __shared__ uint4 sB[2][SG * 256];
+  __shared__ double sMass[64];
+  const int tile = g.nunit_tile[blockIdx.x];
+  if (tile < 0) return;                                    // whole block: no barrier is skipped
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, w4 = wave & 3, half = wave >> 2;
+  const int col = lane & 15, kq = lane >> 4, rhs = blockIdx.z;
+  const int mt0 = g.nunit_mt[blockIdx.x];
+  const int NL = g.n_leaves, Sf = g.split_sf;
+  const int s0 = g.nslot_ptr[tile], s1 = g.nslot_ptr[tile + 1], nitems = (s1 - s0) * NCH;
+  const int nsl = g.tile_nsl[tile], Sv = nsl & 255, Sd = (nsl >> 8) & 255, Smax = Sv > Sd ? Sv : Sd;
+  int Si[TPW];
+  size_t arow[TPW];                                        // A offset of each row tile (in 16-byte units)
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) tns[i] = i >= ni ? 0 : ((mtg + wave + 4 * i) * 16 < P ? nsl_v : nsl_d);
-  const uint4 *Ab = (const uint4 *)t.near_bf16;
-  // A slice fragments of row tile i (rows beyond the tables read tile 0: zero work is masked later)
-  auto a_base = [&](int op, int a, int i, int c_) -> size_t {
-    const int mt = mtg + wave + 4 * (i < ni ? i : 0);
-    return ((((size_t)op * SMAX + a) * MTR + (mt < MTR ? mt : 0)) * NCU + c_) * NST * 64 + lane;
-  };
+  for (int i = 0; i < TPW; ++i) {
+    const int mt = mt0 + w4 + 4 * i;
+    Si[i] = mt >= MTR ? 0 : (mt * 16 < P ? Sv : Sd);
+    arow[i] = (size_t)(mt < MTR ? mt : 0) * NCH * 64 + lane;
+  }
+  const int8_t *fr = fsl + (size_t)rhs * Sf * NL * P;
+  const i32x4 *Atab = (const i32x4 *)t.near_i8;
+  const int *nslot_cfg = g.nslot_cfg, *nslot_src = g.nslot_src;
+  const size_t cfg_stride = (size_t)NEAR_SMAX * MTR * NCH * 64, sl_stride = (size_t)MTR * NCH * 64;
 
-  dbl4 acc[TPW][4];
+  i32x4 acc[TPW][2][SG];
 #pragma unroll
   for (int i = 0; i < TPW; ++i)
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[i][nt] = dbl4{0, 0, 0, 0};
-  double mpart = 0.0;
-  Regs<PERT> rb;
-  int sl = s0, c = 0;
-  if (sl < s1) rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, sl, 0, P, K2, sq, sinv_h2);
-  while (sl < s1) {
-    const int type = slot_type[sl], K = type == 0 ? P : K2, NC = K / KC;
-    __syncthreads();                               // the previous chunk's readers are done
-    {
-      const double *mw = leaf_mass + (size_t)slot_op[sl] * kmax + c * KC + sq * PERT;
+    for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-      for (int j = 0; j < PERT; ++j) mpart = fma(mw[j], rb.v[j], mpart);
-      if (type == 0) {   // samples: slices with their true scales 2^(Ef - 8(b+1))
-        const int src = slot_src[sl * LEAF_TILE];
-        const double sc = src >= 0 ? fs[src] : 1.0, inv = src >= 0 ? 1.0 / sc : 0.0;
-        double r[PERT];
+      for (int d = 0; d < SG; ++d) acc[i][nt][d] = i32x4{0, 0, 0, 0};
+  double mU = 0.0;
+
+  // staging of item j (slot s0 + j / NCH, chunk j % NCH): piece q = tid + 512 m
+  // is 16 bytes (k 16 kq'..) of slice b of column c'
+  uint4 stg[PPT];
+  bool sok[PPT];
+  auto stage_load = [&](int j) {
+    const int sl = s0 + j / NCH, ch = j % NCH;
 #pragma unroll
-        for (int j = 0; j < PERT; ++j) r[j] = rb.v[j] * inv;
-        double p2 = sc;
-        for (int b = 0; b < nsl; ++b) {
-          p2 *= 1.0 / 256.0;
-          uint4 *dst = (uint4 *)(sH + ((size_t)b * LEAF_TILE + scol) * SBH + sq * PERT);
-#pragma unroll
-          for (int j8 = 0; j8 < PERT / 8; ++j8) {
-            uint32_t w[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              uint32_t hv[2];
-#pragma unroll
-              for (int e = 0; e < 2; ++e) {
-                const int j = j8 * 8 + 2 * q + e;
-                const double v = r[j] * 256.0, tr = trunc(v);
-                r[j] = v - tr;
-                hv[e] = bf16_bits(tr * p2);
-              }
-              w[q] = hv[0] | (hv[1] << 16);
-            }
-            dst[j8] = make_uint4(w[0], w[1], w[2], w[3]);
-          }
-        }
-      } else {
-        double *dst = sB + scol * SB + sq * PERT;
-#pragma unroll
-        for (int j = 0; j < PERT; ++j) dst[j] = rb.v[j];
-      }
+    for (int m = 0; m < PPT; ++m) {
+      const int q = tid + 512 * m, b = q >> 8, c = (q >> 2) & 63, kk = q & 3;
+      const int src = nslot_src[sl * 64 + c];
+      sok[m] = src >= 0;
+      const int bb = b < Sf ? b : Sf - 1;
+      stg[m] = *(const uint4 *)(fr + ((size_t)bb * NL + (src >= 0 ? src : 0)) * P + ch * 64 + kk * 16);
     }
-    __syncthreads();
-    int nsl2 = sl, nc = c + 1;
-    if (nc >= NC) { ++nsl2; nc = 0; }
-    if (nsl2 < s1) rb = leaf_chunk_load<KC>(slot_type, slot_src, fr, Lr, Mr, nsl2, nc, P, K2, sq, sinv_h2);
-    if (type == 0) {
-      // slice pairs (a, b) in order of d = a + b; one exact FP32 sum per group d
-      const int op = slot_op[sl];
-      flt4 g32[TPW][4];
+  };
+  auto stage_write = [&](int buf) {
 #pragma unroll
-      for (int i = 0; i < TPW; ++i)
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) g32[i][nt] = flt4{0, 0, 0, 0};
-      uint4 an[TPW][NST];
-#pragma unroll
-      for (int i = 0; i < TPW; ++i)
-#pragma unroll
-        for (int st = 0; st < NST; ++st) an[i][st] = Ab[a_base(op, 0, i, c) + st * 64];
-#pragma unroll
-      for (int pi = 0; pi < SMAX * (SMAX + 1) / 2; ++pi) {
-        // pair pi: group d, a = pi - d(d+1)/2, b = d - a
-        int d = 0;
-        while ((d + 1) * (d + 2) / 2 <= pi) ++d;
-        const int a = pi - d * (d + 1) / 2, b = d - a;
-        if (d >= nsl) break;
-        bf16x8 av[TPW][NST];
-#pragma unroll
-        for (int i = 0; i < TPW; ++i)
-#pragma unroll
-          for (int st = 0; st < NST; ++st) av[i][st] = __builtin_bit_cast(bf16x8, an[i][st]);
-        {   // next pair's table slice in flight
-          int d2 = 0;
-          while ((d2 + 1) * (d2 + 2) / 2 <= pi + 1) ++d2;
-          const int a2 = pi + 1 - d2 * (d2 + 1) / 2;
-          if (pi + 1 < SMAX * (SMAX + 1) / 2 && d2 < nsl) {
-#pragma unroll
-            for (int i = 0; i < TPW; ++i)
-#pragma unroll
-              for (int st = 0; st < NST; ++st) an[i][st] = Ab[a_base(op, a2, i, c) + st * 64];
-          }
-        }
-#pragma unroll
-        for (int st = 0; st < NST; ++st)
-#pragma unroll
-          for (int nt = 0; nt < 4; ++nt) {
-            const uint4 u = *(const uint4 *)(sH + ((size_t)b * LEAF_TILE + nt * 16 + col) * SBH + st * 32 + kq * 8);
-            const bf16x8 bv = __builtin_bit_cast(bf16x8, u);
-#pragma unroll
-            for (int i = 0; i < TPW; ++i)
-              if (d < tns[i]) g32[i][nt] = mfma_bf16(av[i][st], bv, g32[i][nt]);
-          }
-        if (a == d) {   // last pair of group d: add its exact sum
-#pragma unroll
-          for (int i = 0; i < TPW; ++i)
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-#pragma unroll
-              for (int r = 0; r < 4; ++r) acc[i][nt][r] += (double)g32[i][nt][r];
-              g32[i][nt] = flt4{0, 0, 0, 0};
-            }
-        }
-      }
-    } else {
-      const double *A = leaf_frag + slot_aoff[sl];
-#pragma unroll 4
-      for (int ks = 0; ks < KSC; ++ks) {
-        double av[TPW];
-#pragma unroll
-        for (int i = 0; i < TPW; ++i)
-          av[i] = A[(((size_t)(mtg + wave + 4 * (i < ni ? i : 0)) * NC + c) * KSC + ks) * 64 + lane];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-          const double b = sB[(nt * 16 + col) * SB + kq * KSC + ks];
-#pragma unroll
-          for (int i = 0; i < TPW; ++i)
-            if (i < ni) acc[i][nt] = mfma4(av[i], b, acc[i][nt]);
-        }
-      }
+    for (int m = 0; m < PPT; ++m) {
+      const int q = tid + 512 * m, b = q >> 8, c = (q >> 2) & 63, kk = q & 3;
+      sB[buf][b * 256 + c * 4 + (kk ^ ((c >> 2) & 3))] = sok[m] ? stg[m] : make_uint4(0, 0, 0, 0);
     }
-    sl = nsl2;
-    c = nc;
+  };
+  i32x4 ar[3][TPW];
+  auto a_load = [&](int reg, int j, int a) {
+    const int sl = s0 + j / NCH, ch = j % NCH;
+    const size_t base = (size_t)nslot_cfg[sl] * cfg_stride + (size_t)a * sl_stride + ch * 64;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) ar[reg][i] = Atab[base + arow[i]];
+  };
+
+  if (nitems > 0) {
+    stage_load(0);
+    stage_write(0);
+    stage_load(nitems > 1 ? 1 : 0);
+    a_load(0, 0, SEQ[0]);
+    a_load(1, 0, SEQ[1]);
   }
-  mpart += __shfl_xor(mpart, 1);
-  mpart += __shfl_xor(mpart, 2);
-  if (sq == 0) sMass[scol] = mpart;
-  __syncthreads();
+  for (int j = 0; j < nitems; ++j) {
+    const int buf = j & 1, jn = j + 1 < nitems ? j + 1 : j, jnn = j + 2 < nitems ? j + 2 : jn;
+    __syncthreads();                                       // item j staged; buffer buf ^ 1 free
+    if (j + 1 < nitems) stage_write(buf ^ 1);
+    if (tid < 64 && j % NCH == 0) {                        // mass weights of this slot's sources
+      const int sl = s0 + j / NCH, src = nslot_src[sl * 64 + tid];
+      if (src >= 0) mU = fma(t.split_cfg_w2[nslot_cfg[sl]], lmass[(size_t)rhs * NL + src], mU);
+    }
+    const uint4 *S = sB[buf];
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    const int tgt = g.tile_tgt[tile * LEAF_TILE + nt * 16 + col];
+    for (int idx = 0; idx < SG; ++idx) {
+      const int a = SEQ[idx];
+      // fragments two iterations ahead (the next item's first two at the end)
+      if (idx + 2 < SG) a_load((idx + 2) % 3, j, SEQ[idx + 2]);
+      else a_load((idx + 2) % 3, jn, SEQ[idx + 2 - SG]);
+      if (idx == 1) stage_load(jnn);
+      if (a < Smax) {
+#pragma unroll
+        for (int b = 0; b < SG - a; ++b) {
+          if (a + b >= Smax) break;
+          i32x4 bv[2];
+#pragma unroll
+          for (int nt = 0; nt < 2; ++nt) {
+            const int c = (2 * half + nt) * 16 + col;
+            bv[nt] = __builtin_bit_cast(i32x4, S[b * 256 + c * 4 + (kq ^ ((c >> 2) & 3))]);
+          }
+#pragma unroll
+          for (int i = 0; i < TPW; ++i)
+            if (a + b < Si[i]) {
+#pragma unroll
+              for (int nt = 0; nt < 2; ++nt) acc[i][nt][a + b] = mfma_i8(ar[idx % 3][i], bv[nt], acc[i][nt][a + b]);
+            }
+        }
+      }
+    }
+  }
+  if (tid < 64) sMass[tid] = mU;
+  __syncthreads();
+  const double fsc = fscale[rhs];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    const int c = (2 * half + nt) * 16 + col;
+    const int tgt = g.tile_tgt[tile * LEAF_TILE + c];
     if (tgt < 0) continue;
     const double h = box_h(g.width, g.leaf_level[tgt]);
-    const double lg = h * h * log(h) * kInv2Pi * sMass[nt * 16 + col];
-    double *Vt = V + ((size_t)rhs * g.n_leaves + tgt) * P;
-    double *Gt = G + ((size_t)rhs * g.n_leaves + tgt) * 2 * P;
+    const double lg = h * h * log(h) * kInv2Pi * sMass[c];
+    double *Vt = V + ((size_t)rhs * NL + tgt) * P;
+    double *Gt = G + ((size_t)rhs * NL + tgt) * 2 * P;
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
-      const int mt = mtg + wave + 4 * i;
-      if (i >= ni || mt >= MTR) continue;
+      const int mt = mt0 + w4 + 4 * i;
+      if (mt >= MTR) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = mt * 16 + 4 * kq + r;
-        if (row < P) Vt[row] = h * h * acc[i][nt][r] + lg;
-        else Gt[row - P] = h * acc[i][nt][r];
+        const int row = mt * 16 + 4 * kq + r;             // D[4 (lane / 16) + r][lane % 16]
+        const double rs = t.split_row_scale[row] * fsc;
+        double v = 0.0;
+#pragma unroll
+        for (int d = SG - 1; d >= 0; --d)
+          if (d < Si[i]) v += (double)acc[i][nt][d][r] * ldexp(rs, -7 * (d + 2));
+        if (row < P) Vt[row] = h * h * v + lg;
+        else Gt[row - P] = h * v;
       }
     }
   }
@@ -757,28 +756,35 @@ void launch_l2l(const DevTables &t, const DevTree &g, const int *boxes, int nbox
   else hipLaunchKernelGGL(l2l_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, boxes, nbox, L);
 }
 void launch_leaf(const DevTables &t, const DevTree &g, const double *f, int nrhs, const double *M,
-                 const double *L, double *V, double *G, hipStream_t s) {
+                 const double *L, double *V, double *G, bool accumulate, hipStream_t s) {
+  const int acc = accumulate ? 1 : 0;
   if (g.n_units <= 0) return;
   const dim3 grid(g.n_units, 1, nrhs);      // one work unit per block (a multiple of the 8 XCDs)
   if (t.n == 4) {         // 3 row tiles, K chunks of 16
-    hipLaunchKernelGGL((leaf_mfma_kernel<1, 16>), grid, dim3(256), 0, s, t, g, f, M, L, V, G);
+    hipLaunchKernelGGL((leaf_mfma_kernel<1, 16>), grid, dim3(256), 0, s, t, g, f, M, L, V, G, acc);
   } else if (t.n == 8) {  // 12 row tiles: 3 per wave
-    hipLaunchKernelGGL((leaf_mfma_kernel<3, 64>), grid, dim3(256), 0, s, t, g, f, M, L, V, G);
+    hipLaunchKernelGGL((leaf_mfma_kernel<3, 64>), grid, dim3(256), 0, s, t, g, f, M, L, V, G, acc);
   } else {                // 48 row tiles: groups of 16, 4 per wave
-    hipLaunchKernelGGL((leaf_mfma_kernel<4, 64>), grid, dim3(256), 0, s, t, g, f, M, L, V, G);
+    hipLaunchKernelGGL((leaf_mfma_kernel<4, 64>), grid, dim3(256), 0, s, t, g, f, M, L, V, G, acc);
   }
 }
 
-void launch_leaf_split(const DevTables &t, const DevTree &g, const double *f, double *fscale, int nrhs,
-                       const double *M, const double *L, double *V, double *G, hipStream_t s) {
-  hipLaunchKernelGGL(leaf_scale_kernel, dim3(g.n_leaves, nrhs), dim3(64), 0, s, f, t.P, g.n_leaves, fscale);
-  if (g.n_units <= 0) return;
-  const dim3 grid(g.n_units, 1, nrhs);
-  if (t.n == 8) {
-    hipLaunchKernelGGL((leaf_split_kernel<3, 64>), grid, dim3(256), 0, s, t, g, f, fscale, M, L, V, G);
-  } else {
-    hipLaunchKernelGGL((leaf_split_kernel<4, 64>), grid, dim3(256), 0, s, t, g, f, fscale, M, L, V, G);
-  }
+void launch_split_prep(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *fpart,
+                       double *fscale, int8_t *fsl, double *lmass, hipStream_t s) {
+  const size_t count = (size_t)g.n_leaves * t.P;
+  const int nparts = (int)std::min<size_t>(FMAX_BLOCKS, (count + 2047) / 2048);
+  hipLaunchKernelGGL(fmax_partial_kernel, dim3(nparts, nrhs), dim3(256), 0, s, f, count, fpart);
+  const int lpb = t.P >= 256 ? 1 : 256 / t.P;
+  hipLaunchKernelGGL(split_prep_kernel, dim3((g.n_leaves + lpb - 1) / lpb, nrhs), dim3(256), 0, s, f, t.wq, t.P,
+                     g.n_leaves, fpart, nparts, g.split_sf, fscale, fsl, lmass);
+}
+
+void launch_leaf_near_i8(const DevTables &t, const DevTree &g, const int8_t *fsl, const double *lmass,
+                         const double *fscale, int nrhs, double *V, double *G, hipStream_t s) {
+  if (g.n_nunits <= 0) return;
+  const dim3 grid(g.n_nunits, 1, nrhs);
+  if (t.n == 8) hipLaunchKernelGGL((leaf_near_i8_kernel<3, 1>), grid, dim3(512), 0, s, t, g, fsl, lmass, fscale, V, G);
+  else hipLaunchKernelGGL((leaf_near_i8_kernel<3, 4>), grid, dim3(512), 0, s, t, g, fsl, lmass, fscale, V, G);
 }
 
 }  // namespace bx

@@ -535,64 +535,75 @@ void build_leaf_frag(const Tables &T, std::vector<double> &out, std::vector<doub
   }
 }
 
-static uint16_t bf16_bits_scaled(double v, double pow2) {
-  // v is an integer with |v| <= 256 and pow2 a power of two: v * pow2 is exact in
-  // float and in BF16 (the upper half of the float) while it stays a normal number
-  float f = (float)(v * pow2);
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  return (uint16_t)(u >> 16);
-}
-
 void build_split_tables(const Tables &T, SplitTables &S) {
-  const LeafFragLayout L = leaf_frag_layout(T.n, T.p);
-  const int P = T.P, MR = T.MR, KC = L.KC, NC = P / KC, MTR = 3 * P / 16;
-  double mv = 0.0, md = 0.0;
+  const int P = T.P, MR = T.MR, R = 3 * P, MTR = R / 16, NCH = P / 64;
+  Rel cfg[NCFG_U];
+  u_configs(cfg);
+  S.cfg_w2.resize(NCFG_U);
+  for (int c = 0; c < NCFG_U; ++c) S.cfg_w2[c] = cfg[c].w * cfg[c].w;
+  auto X = [&](int c, int r, int k) { return T.near_[((size_t)c * MR + r) * P + k]; };
+  // row scales 2^E_r with max |x| <= 2^E_r * 127.5/128, so that the leading
+  // rounded slice stays within [-127, 127]
+  S.row_scale.assign(R, 1.0);
+  for (int r = 0; r < R; ++r) {
+    double m = 0.0;
+    for (int c = 0; c < NCFG_U; ++c)
+      for (int k = 0; k < P; ++k) m = std::max(m, std::fabs(X(c, r, k)));
+    if (m == 0.0) continue;
+    int e;
+    const double fr = std::frexp(m, &e);
+    if (fr * 128.0 >= 127.5) ++e;
+    S.row_scale[r] = std::ldexp(1.0, e);
+  }
+  // slices: x / 2^E_r = sum_a t_a 2^-7(a+1) + residual, t_a = nearest integers
+  // (|t_0| <= 127, |t_a| <= 64 after), and for each row the sums over all
+  // configurations and k of |t_a|, of |x - X_s| and of |X_s| (X_s: s slices)
+  std::vector<double> sum_t((size_t)R * SPLIT_SMAX, 0.0), sum_res((size_t)R * (SPLIT_SMAX + 1), 0.0),
+      sum_abs((size_t)R * (SPLIT_SMAX + 1), 0.0);
+  S.a.assign((size_t)NCFG_U * SPLIT_SMAX * MTR * NCH * 64 * 16, 0);
   for (int c = 0; c < NCFG_U; ++c)
-    for (int i = 0; i < 3 * P; ++i)
+    for (int r = 0; r < R; ++r)
       for (int k = 0; k < P; ++k) {
-        double v = std::fabs(T.near_[((size_t)c * MR + i) * P + k]);
-        if (i < P) mv = std::max(mv, v); else md = std::max(md, v);
+        const double x = X(c, r, k), E = S.row_scale[r];
+        double v = x / E, approx = 0.0;
+        const int mt = r / 16, i = r % 16, ch = k / 64, kk = k % 64, lane = i + 16 * (kk / 16), e = kk % 16;
+        for (int a = 0; a < SPLIT_SMAX; ++a) {
+          const double sc = v * 128.0, t = std::nearbyint(sc);
+          v = sc - t;
+          S.a[(((((size_t)c * SPLIT_SMAX + a) * MTR + mt) * NCH + ch) * 64 + lane) * 16 + e] = (int8_t)t;
+          sum_t[(size_t)r * SPLIT_SMAX + a] += std::fabs(t);
+          approx += t * std::ldexp(E, -7 * (a + 1));
+          sum_res[(size_t)r * (SPLIT_SMAX + 1) + a + 1] += std::fabs(x - approx);
+          sum_abs[(size_t)r * (SPLIT_SMAX + 1) + a + 1] += std::fabs(approx);
+        }
       }
-  int ev, ed;
-  std::frexp(mv, &ev);
-  std::frexp(md, &ed);
-  S.scale_v = std::ldexp(1.0, ev);
-  S.scale_d = std::ldexp(1.0, ed);
-  // error bound factor: a target's near field uses at most 13 configurations, each K terms
-  S.bound_v = 13.0 * P * S.scale_v;
-  S.bound_d = 13.0 * P * S.scale_d;
-  S.a.assign((size_t)NCFG_U * SPLIT_SMAX * MTR * NC * 2 * 64 * 8, 0);
-  for (int c = 0; c < NCFG_U; ++c)
-    for (int mt = 0; mt < MTR; ++mt)
-      for (int ch = 0; ch < NC; ++ch)
-        for (int st = 0; st < 2; ++st)
-          for (int lane = 0; lane < 64; ++lane)
-            for (int e = 0; e < 8; ++e) {
-              const int row = mt * 16 + (lane & 15), k = ch * KC + st * 32 + (lane >> 4) * 8 + e;
-              const double E = row < P ? S.scale_v : S.scale_d;
-              double r = k < P ? T.near_[((size_t)c * MR + row) * P + k] / E : 0.0;
-              for (int a = 0; a < SPLIT_SMAX; ++a) {
-                const double sc = r * 256.0, sl = std::trunc(sc);
-                r = sc - sl;
-                // slice with its true scale: an integer times a power of two, exact in BF16
-                S.a[((((((size_t)c * SPLIT_SMAX + a) * MTR + mt) * NC + ch) * 2 + st) * 64 + lane) * 8 + e] =
-                    bf16_bits_scaled(sl, E * std::ldexp(1.0, -8 * (a + 1)));
-              }
-            }
+  // error bound per slice count s, for samples |y| < 1 rounded to s slices the
+  // same way: table residual + sample residual (<= 2^-7s / 2 per sample) + the
+  // dropped pairs a + b >= s (a, b < s; |s_0| <= 127, |s_b| <= 64 after)
+  S.err_v.assign(SPLIT_SMAX + 1, 0.0);
+  S.err_d.assign(SPLIT_SMAX + 1, 0.0);
+  for (int sn = 1; sn <= SPLIT_SMAX; ++sn)
+    for (int r = 0; r < R; ++r) {
+      double e = sum_res[(size_t)r * (SPLIT_SMAX + 1) + sn] +
+                 sum_abs[(size_t)r * (SPLIT_SMAX + 1) + sn] * 0.5 * std::ldexp(1.0, -7 * sn);
+      for (int a = 0; a < sn; ++a)
+        for (int b = sn - a; b < sn; ++b)
+          e += sum_t[(size_t)r * SPLIT_SMAX + a] * std::ldexp(S.row_scale[r], -7 * (a + 1)) * (b == 0 ? 127.0 : 64.0) *
+               std::ldexp(1.0, -7 * (b + 1));
+      double &dst = r < P ? S.err_v[sn] : S.err_d[sn];
+      dst = std::max(dst, e);
+    }
 }
 
 int split_slices(const SplitTables &S, int level, double tol, bool grad_rows) {
-  // truncating x and y to S slices and dropping slice pairs with a + b >= S
-  // leaves at most (S + 1) 2^-8S 2^(Ex + Ey) per product term; V rows carry h^2,
-  // gradient rows h
-  const double h = std::ldexp(1.0, -level);
-  for (int s = 1; s <= SPLIT_SMAX; ++s) {
-    const double e = (s + 1) * std::ldexp(1.0, -8 * s);
-    if (!grad_rows && h * h * S.bound_v * 2.0 * e <= tol) return s;
-    if (grad_rows && h * S.bound_d * 2.0 * e <= tol) return s;
+  // the sample scale 2^Ef is at most 2 (128/127.5) max |f|; values carry h^2,
+  // gradients h (h = 2^-level of the root width)
+  const double h = std::ldexp(1.0, -level), fs = 2.0 * 128.0 / 127.5;
+  for (int sn = 1; sn <= SPLIT_SG; ++sn) {
+    const double e = (grad_rows ? h * S.err_d[sn] : h * h * S.err_v[sn]) * fs;
+    if (e <= tol) return sn;
   }
-  return SPLIT_SMAX;
+  return 0;
 }
 
 void build_p2m_frag(const Tables &T, std::vector<double> &out) {

@@ -168,7 +168,7 @@ SPLIT_TOL = 1e-10
 @pytest.fixture(scope="module")
 def ctx8s():
     _torch()
-    return B.Context(8, 30, B.BX_SPLIT_BF16)
+    return B.Context(8, 30, B.BX_SPLIT_INT8)
 
 
 @pytest.mark.parametrize("case", ["uniform4_gauss", "graded_random"])

@@ -303,11 +303,69 @@ def test_l2t_m2t_p2l_p2m_against_direct_sums():
     assert np.abs(Vl - Vo).max() < 1e-12
 
 
+def _split_tables(n=8, p=16):
+    ctx = B.Context(n, p, B.BX_SPLIT_INT8 | B.BX_HOST_ONLY)
+    P = n * n
+    sl = ctx.table("split_slices").reshape(33, 8, 3 * P, P)
+    rs = ctx.table("split_row_scale")
+    err = ctx.table("split_err").reshape(2, 9)
+    near = ctx.table("near").reshape(33, -1, P)[:, :3 * P, :]
+    return ctx, sl, rs, err, near
+
+
 def test_split_slices_reconstruct_tables():
-    # The BF16 slices of the near tables: integers |s| <= 256, and
-    # scale * sum_a s_a 2^-8(a+1) reproduces every table entry to the truncation bound.
-    ctx = B.Context(8, 16, B.BX_SPLIT_BF16 | B.BX_HOST_ONLY)
+    # int8 slices of the near tables: integers, |s_0| <= 127 and |s_a| <= 64
+    # after (rounded to nearest), and with S slices every entry is within half a
+    # unit of the last slice, scale_r 2^-7S / 2.
+    ctx, sl, rs, err, near = _split_tables()
+    assert np.array_equal(sl, np.round(sl))
+    assert np.abs(sl[:, 0]).max() <= 127 and np.abs(sl[:, 1:]).max() <= 64
+    assert np.all(np.abs(near).max(axis=(0, 2)) <= rs * 127.5 / 128)
+    w = 2.0 ** (-7 * (np.arange(8) + 1))
+    for S in range(1, 9):
+        approx = np.einsum("cask,a->csk", sl[:, :S], w[:S]) * rs[None, :, None]
+        assert np.all(np.abs(near - approx) <= 0.5 * 2.0 ** (-7 * S) * rs[None, :, None] * (1 + 1e-12) + 1e-300)
     tr = B.Tree.from_inputs(ctx, I.point_refined_tree([[0.3, 0.2]], [6]))
     assert tr.query("split_products") >= 1
     with pytest.raises(B.BoxFMMError):
-        B.Context(4, 16, B.BX_SPLIT_BF16 | B.BX_HOST_ONLY, build=False)
+        B.Context(4, 16, B.BX_SPLIT_INT8 | B.BX_HOST_ONLY, build=False)
+
+
+def test_split_error_bound_holds():
+    # The slice-pair sum sum_{a+b<S} t_a s_b 2^-7(a+b+2) (samples |y| < 1 rounded
+    # to slices the same way) differs from the exact T y by at most the stated
+    # bound, for every row, with all 33 configurations at once (the bound's
+    # worst case) and for sample patterns aligned with the table signs.
+    ctx, sl, rs, err, near = _split_tables()
+    P = near.shape[2]
+    rng = np.random.default_rng(7)
+
+    def slices(y, S):
+        out, v = [], y.copy()
+        for _ in range(S):
+            t = np.rint(v * 128)
+            out.append(t)
+            v = v * 128 - t
+        return out
+
+    for S in (3, 4, 5, 6):
+        for trial in range(4):
+            if trial < 2:
+                y = rng.uniform(-1, 1, size=(33, P)) * (127.5 / 128)
+            else:   # signs of the table row that the bound is tightest for, magnitudes near 1
+                r = rng.integers(0, 3 * P)
+                y = np.sign(near[:, r, :] + 1e-300) * (127.4 / 128) * (1 - 0.01 * rng.random((33, P)))
+            ys = slices(y, S)
+            exact = np.einsum("crk,ck->r", near, y)
+            approx = np.zeros(3 * P)
+            for a_ in range(S):
+                for b_ in range(S - a_):
+                    approx += np.einsum("crk,ck->r", sl[:, a_], ys[b_]) * 2.0 ** (-7 * (a_ + b_ + 2))
+            approx *= rs
+            e = np.abs(exact - approx)
+            assert e[:P].max() <= err[0, S] * (1 + 1e-6) + 1e-15, (S, trial)
+            assert e[P:].max() <= err[1, S] * (1 + 1e-6) + 1e-15, (S, trial)
+    # the bounds fall by about 2^7 per slice
+    for k in (0, 1):
+        ratio = err[k, 3:7] / err[k, 4:8]
+        assert np.all(ratio > 50) and np.all(ratio < 300)
