@@ -188,6 +188,7 @@ int bx_build_tables(bx_ctx *ctx, double quad_tol, const char *cache_dir) {
   build_l2l_frag(T, llf);
   build_p2l_frag(T, xf);
   d.leaf_kmax = leaf_frag_layout(T.n, T.p).KMAX;
+  d.leaf_kc = leaf_frag_layout(T.n, T.p).KC;
   if ((rc = upload(ctx->dev, lf, &d.leaf_frag, s)) || (rc = upload(ctx->dev, lm, &d.leaf_mass, s)) ||
       (rc = upload(ctx->dev, pf, &d.p2m_frag, s)) ||
       (rc = upload(ctx->dev, mf, &d.m2m_frag, s)) || (rc = upload(ctx->dev, llf, &d.l2l_frag, s)) ||
@@ -558,8 +559,7 @@ static int enqueue_eval(bx_ctx *ctx, bx_tree *t, const double *f, int nrhs, doub
   if ((rc = mark(BX_PH_L2L, false)) || (rc = mark(BX_PH_LEAF, true))) return rc;
   if (ctx->flags & BX_SPLIT_INT8) {
     launch_split_prep(d, g, f, nrhs, t->fpart, t->fscale, t->fsl, t->lmass, s);
-    launch_leaf_near_i8(d, g, t->fsl, t->lmass, t->fscale, nrhs, V, G, s);
-    launch_leaf(d, g, f, nrhs, t->M, t->L, V, G, true, s);
+    launch_leaf_split(d, g, t->fsl, t->lmass, t->fscale, f, nrhs, t->M, t->L, V, G, s);
   } else {
     launch_leaf(d, g, f, nrhs, t->M, t->L, V, G, false, s);
   }

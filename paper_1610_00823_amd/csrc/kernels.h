@@ -15,6 +15,7 @@ struct DevTables {
   const double *leaf_frag, *p2m_frag;
   const double *leaf_mass;   // [54][KMAX] mass-row weights of the leaf operators
   int leaf_kmax;
+  int leaf_kc;               // K chunk width of the leaf fragments (divides P and 2 KP)
   // split contexts: int8 slices of the near tables (layout in bx_internal.h),
   // the per-row scales 2^E_r [3P] and the mass factors w_c^2 of the 33 configurations
   const int8_t *near_i8;
@@ -93,8 +94,10 @@ void launch_leaf(const DevTables &t, const DevTree &g, const double *f, int nrhs
 // [n_rhs][512] partial maxima.
 void launch_split_prep(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *fpart,
                        double *fscale, int8_t *fsl, double *lmass, hipStream_t s);
-// Int8 near field of every tile: writes V and G (then launch_leaf accumulates the rest).
-void launch_leaf_near_i8(const DevTables &t, const DevTree &g, const int8_t *fsl, const double *lmass,
-                         const double *fscale, int nrhs, double *V, double *G, hipStream_t s);
+// Split precision leaf phase: int8 near field of every tile, then (in the same
+// kernel, FP64) L2T, the W list and the near field of tiles left in FP64; writes V and G.
+void launch_leaf_split(const DevTables &t, const DevTree &g, const int8_t *fsl, const double *lmass,
+                       const double *fscale, const double *f, int nrhs, const double *M, const double *L, double *V,
+                       double *G, hipStream_t s);
 
 }  // namespace bx

@@ -575,15 +575,21 @@ __global__ void __launch_bounds__(256) split_prep_kernel(const double *__restric
 // 16-lane groups of a 16-byte read hit distinct banks); the A slices stream
 // from the table two iterations ahead, in the slice order 0,5,1,4,2,3 that
 // alternates long and short iterations.
-template <int TPW, int NCH>
+template <int TPW, int NCH, int KCF>
 __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTree g, const int8_t *__restrict__ fsl,
                                                              const double *__restrict__ lmass,
                                                              const double *__restrict__ fscale,
-                                                             double *__restrict__ V, double *__restrict__ G) {
+                                                             const double *__restrict__ f,
+                                                             const double *__restrict__ M,
+                                                             const double *__restrict__ L, double *__restrict__ V,
+                                                             double *__restrict__ G) {
   constexpr int SG = NEAR_SG, P = 64 * NCH, MTR = 3 * P / 16, PPT = SG * 256 / 512;
   constexpr int SEQ[SG] = {0, 5, 1, 4, 2, 3};
-  __shared__ uint4 sB[2][SG * 256];
+  constexpr int KSC = KCF / 4, PERT = KCF / 8, SBF = KCF + 1;   // FP64 phase: chunks of KCF columns
+  constexpr int BYTES_I8 = 2 * SG * 256 * 16, BYTES_F64 = 2 * LEAF_TILE * SBF * 8;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[BYTES_I8 > BYTES_F64 ? BYTES_I8 : BYTES_F64];
   __shared__ double sMass[64];
+  uint4(*sB)[SG * 256] = (uint4(*)[SG * 256])smem;
   const int tile = g.nunit_tile[blockIdx.x];
   if (tile < 0) return;                                    // whole block: no barrier is skipped
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, w4 = wave & 3, half = wave >> 2;
@@ -687,16 +693,130 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
       }
     }
   }
+  // ---- FP64 phase: L2T, the W list and the U slots of tiles left in FP64,
+  // seeded with the scaled int8 group sums.  The FP64 tables' rows are permuted
+  // so that accumulator register r of a lane holds row 4 (lane / 16) + r, the
+  // int8 layout, and the sums move over in place.
+  const double fsc = fscale[rhs];
+  dbl4 fa[TPW][2];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int mt = mt0 + w4 + 4 * i;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = (mt < MTR ? mt : 0) * 16 + 4 * kq + r;
+        const double rs = t.split_row_scale[row] * fsc;
+        double v = 0.0;
+#pragma unroll
+        for (int d = SG - 1; d >= 0; --d)
+          if (d < Si[i]) v += (double)acc[i][nt][d][r] * ldexp(rs, -7 * (d + 2));
+        fa[i][nt][r] = v;
+      }
+  }
+  double *sF = (double *)smem;                             // [2][64 * SBF]
+  const int scol = tid >> 3, sq = tid & 7;                 // staging: 8 threads per column
+  const int stgt = g.tile_tgt[tile * LEAF_TILE + scol];
+  const double sh = stgt >= 0 ? box_h(g.width, g.leaf_level[stgt]) : 1.0;
+  const double sinv_h2 = stgt >= 0 ? 1.0 / (sh * sh) : 0.0;
+  const int f0 = g.tile_ptr[tile], f1 = g.tile_ptr[tile + 1], K2 = 2 * t.KP;
+  const int *slot_type = g.slot_type, *slot_op = g.slot_op, *slot_aoff = g.slot_aoff, *slot_src = g.slot_src + scol;
+  const double *fr64 = f + (size_t)rhs * NL * P;
+  const double *Lr = L + (size_t)rhs * g.n_boxes * K2, *Mr = M + (size_t)rhs * g.n_boxes * K2;
+  const double *leaf_frag = t.leaf_frag, *leaf_mass = t.leaf_mass;
+  const int kmax = t.leaf_kmax;
+  double mpart = 0.0;
+  Regs<PERT> rb;
+  double an[2][TPW];
+  auto f64_a = [&](int sl_, int c_) -> const double * {
+    const int NC_ = (slot_type[sl_] == 0 ? P : K2) / KCF;
+    return leaf_frag + slot_aoff[sl_] + ((size_t)(mt0 + w4) * NC_ + c_) * KSC * 64 + lane;
+  };
+  auto f64_stride = [&](int sl_) -> size_t {
+    const int NC_ = (slot_type[sl_] == 0 ? P : K2) / KCF;
+    return (size_t)4 * NC_ * KSC * 64;
+  };
+  auto f64_b = [&](int sl_, int c_) {
+    const int type = slot_type[sl_], src = slot_src[sl_ * LEAF_TILE];
+    const double *bp = type == 0 ? fr64 + (size_t)(src >= 0 ? src : 0) * P
+                                 : (type == 1 ? Lr : Mr) + (size_t)(src >= 0 ? src : 0) * K2;
+    const double sc = src < 0 ? 0.0 : (type == 0 ? 1.0 : sinv_h2);
+    const double *q = bp + c_ * KCF + sq * PERT;
+#pragma unroll
+    for (int j = 0; j < PERT; ++j) rb.v[j] = sc * q[j];
+  };
+  int sl = f0, c = 0, buf = 0;
+  __syncthreads();                                         // the int8 buffers are no longer read
+  if (sl < f1) {
+    const double *A0 = f64_a(sl, 0);
+    const size_t st0 = f64_stride(sl);
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) an[jj][i] = A0[i * st0 + jj * 64];
+    f64_b(sl, 0);
+  }
+  while (sl < f1) {
+    const int NC = (slot_type[sl] == 0 ? P : K2) / KCF;
+    {
+      const double *mw = leaf_mass + (size_t)slot_op[sl] * kmax + c * KCF + sq * PERT;
+      double *dst = sF + buf * LEAF_TILE * SBF + scol * SBF + sq * PERT;
+#pragma unroll
+      for (int j = 0; j < PERT; ++j) {
+        dst[j] = rb.v[j];
+        mpart = fma(mw[j], rb.v[j], mpart);
+      }
+    }
+    __syncthreads();
+    int nsl = sl, nc = c + 1;
+    if (nc >= NC) { ++nsl; nc = 0; }
+    const bool more = nsl < f1;
+    const double *Ac = f64_a(sl, c);
+    const size_t stc = f64_stride(sl);
+    const double *An = more ? f64_a(nsl, nc) : Ac;
+    const size_t stn = more ? f64_stride(nsl) : stc;
+    if (more) f64_b(nsl, nc);
+    const double *Sx = sF + buf * LEAF_TILE * SBF;
+#pragma unroll
+    for (int ks = 0; ks < KSC; ++ks) {
+      double a[TPW];
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) a[i] = an[ks % 2][i];
+      if (ks + 2 < KSC) {
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) an[ks % 2][i] = Ac[i * stc + (ks + 2) * 64];
+      } else if (more) {
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) an[ks % 2][i] = An[i * stn + (ks + 2 - KSC) * 64];
+      }
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        const double b = Sx[((2 * half + nt) * 16 + col) * SBF + kq * KSC + ks];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) fa[i][nt] = mfma4(a[i], b, fa[i][nt]);
+      }
+    }
+    sl = nsl;
+    c = nc;
+    buf ^= 1;
+  }
+  // mass per column: the U part (threads < 64) plus the FP64 slots' part
+  mpart += __shfl_xor(mpart, 1);
+  mpart += __shfl_xor(mpart, 2);
+  mpart += __shfl_xor(mpart, 4);
+  __syncthreads();
   if (tid < 64) sMass[tid] = mU;
   __syncthreads();
-  const double fsc = fscale[rhs];
+  if (sq == 0) sMass[scol] += mpart;
+  __syncthreads();
 #pragma unroll
   for (int nt = 0; nt < 2; ++nt) {
-    const int c = (2 * half + nt) * 16 + col;
-    const int tgt = g.tile_tgt[tile * LEAF_TILE + c];
+    const int cc = (2 * half + nt) * 16 + col;
+    const int tgt = g.tile_tgt[tile * LEAF_TILE + cc];
     if (tgt < 0) continue;
     const double h = box_h(g.width, g.leaf_level[tgt]);
-    const double lg = h * h * log(h) * kInv2Pi * sMass[c];
+    const double lg = h * h * log(h) * kInv2Pi * sMass[cc];
     double *Vt = V + ((size_t)rhs * NL + tgt) * P;
     double *Gt = G + ((size_t)rhs * NL + tgt) * 2 * P;
 #pragma unroll
@@ -705,14 +825,9 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
       if (mt >= MTR) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = mt * 16 + 4 * kq + r;             // D[4 (lane / 16) + r][lane % 16]
-        const double rs = t.split_row_scale[row] * fsc;
-        double v = 0.0;
-#pragma unroll
-        for (int d = SG - 1; d >= 0; --d)
-          if (d < Si[i]) v += (double)acc[i][nt][d][r] * ldexp(rs, -7 * (d + 2));
-        if (row < P) Vt[row] = h * h * v + lg;
-        else Gt[row - P] = h * v;
+        const int row = mt * 16 + 4 * kq + r;
+        if (row < P) Vt[row] = h * h * fa[i][nt][r] + lg;
+        else Gt[row - P] = h * fa[i][nt][r];
       }
     }
   }
@@ -760,12 +875,15 @@ void launch_leaf(const DevTables &t, const DevTree &g, const double *f, int nrhs
   const int acc = accumulate ? 1 : 0;
   if (g.n_units <= 0) return;
   const dim3 grid(g.n_units, 1, nrhs);      // one work unit per block (a multiple of the 8 XCDs)
+  // K chunks of t.leaf_kc columns (a divisor of P and of 2 KP)
   if (t.n == 4) {         // 3 row tiles, K chunks of 16
     hipLaunchKernelGGL((leaf_mfma_kernel<1, 16>), grid, dim3(256), 0, s, t, g, f, M, L, V, G, acc);
   } else if (t.n == 8) {  // 12 row tiles: 3 per wave
-    hipLaunchKernelGGL((leaf_mfma_kernel<3, 64>), grid, dim3(256), 0, s, t, g, f, M, L, V, G, acc);
+    if (t.leaf_kc == 64) hipLaunchKernelGGL((leaf_mfma_kernel<3, 64>), grid, dim3(256), 0, s, t, g, f, M, L, V, G, acc);
+    else hipLaunchKernelGGL((leaf_mfma_kernel<3, 32>), grid, dim3(256), 0, s, t, g, f, M, L, V, G, acc);
   } else {                // 48 row tiles: groups of 16, 4 per wave
-    hipLaunchKernelGGL((leaf_mfma_kernel<4, 64>), grid, dim3(256), 0, s, t, g, f, M, L, V, G, acc);
+    if (t.leaf_kc == 64) hipLaunchKernelGGL((leaf_mfma_kernel<4, 64>), grid, dim3(256), 0, s, t, g, f, M, L, V, G, acc);
+    else hipLaunchKernelGGL((leaf_mfma_kernel<4, 32>), grid, dim3(256), 0, s, t, g, f, M, L, V, G, acc);
   }
 }
 
@@ -779,12 +897,19 @@ void launch_split_prep(const DevTables &t, const DevTree &g, const double *f, in
                      g.n_leaves, fpart, nparts, g.split_sf, fscale, fsl, lmass);
 }
 
-void launch_leaf_near_i8(const DevTables &t, const DevTree &g, const int8_t *fsl, const double *lmass,
-                         const double *fscale, int nrhs, double *V, double *G, hipStream_t s) {
+void launch_leaf_split(const DevTables &t, const DevTree &g, const int8_t *fsl, const double *lmass,
+                       const double *fscale, const double *f, int nrhs, const double *M, const double *L, double *V,
+                       double *G, hipStream_t s) {
   if (g.n_nunits <= 0) return;
   const dim3 grid(g.n_nunits, 1, nrhs);
-  if (t.n == 8) hipLaunchKernelGGL((leaf_near_i8_kernel<3, 1>), grid, dim3(512), 0, s, t, g, fsl, lmass, fscale, V, G);
-  else hipLaunchKernelGGL((leaf_near_i8_kernel<3, 4>), grid, dim3(512), 0, s, t, g, fsl, lmass, fscale, V, G);
+#define BX_NEAR(NCH, KCF)                                                                                        \
+  hipLaunchKernelGGL((leaf_near_i8_kernel<3, NCH, KCF>), grid, dim3(512), 0, s, t, g, fsl, lmass, fscale, f, M, L, \
+                     V, G)
+  if (t.n == 8 && t.leaf_kc == 64) BX_NEAR(1, 64);
+  else if (t.n == 8) BX_NEAR(1, 32);
+  else if (t.leaf_kc == 64) BX_NEAR(4, 64);
+  else BX_NEAR(4, 32);
+#undef BX_NEAR
 }
 
 }  // namespace bx

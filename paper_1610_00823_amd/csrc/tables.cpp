@@ -472,7 +472,8 @@ LeafFragLayout leaf_frag_layout(int n, int p) {
   LeafFragLayout L;
   const int P = n * n, KP = (p + 1 + 15) / 16 * 16;
   L.MTR = (3 * P / 16 + 3) / 4 * 4;                // padded to whole groups of 4 row tiles
-  L.KC = std::min(64, P);
+  // chunk width: a divisor of both K = P (near tables) and K = 2 KP (expansions)
+  L.KC = P == 16 ? 16 : (P == 64 && (2 * KP) % 64 == 0 ? 64 : 32);
   L.KMAX = std::max(P, 2 * KP);
   L.near0 = 0;
   L.near_step = (int64_t)L.MTR * P * 16;           // MTR tiles x K/4 steps x 64 lanes

@@ -136,6 +136,36 @@ def test_adaptive_gaussians_sampled_targets(ctx8):
     assert ev < TOL and ex < TOL and ey < TOL
 
 
+# Other node counts and expansion orders (the K chunking of the leaf GEMM and
+# the expansion operators depend on them).  A graded tree with W and X lists,
+# random samples, a seeded sample of leaves per level against the oracle.  The
+# tolerance is the far-field truncation of order p (measured errors are well
+# below it), and at p = 40 the FP64 bar.
+ORDERS = [(4, 16, B.BX_FP64, 1e-6), (8, 16, B.BX_FP64, 1e-6), (8, 40, B.BX_FP64, TOL),
+          (16, 20, B.BX_FP64, 1e-7), (8, 16, B.BX_SPLIT_INT8, 1e-6), (16, 20, B.BX_SPLIT_INT8, 1e-7)]
+
+
+@pytest.mark.parametrize("n,p,flags,tol", ORDERS, ids=[f"n{o[0]}_p{o[1]}_{'split' if o[2] else 'fp64'}" for o in ORDERS])
+def test_other_orders_sampled(n, p, flags, tol):
+    _torch()
+    ctx = B.Context(n, p, flags)
+    t = I.point_refined_tree([[0.31, 0.22], [-0.4, -0.35]], [5, 3])
+    rng = np.random.default_rng(100 + n + p)
+    f = rng.standard_normal((t.n_leaves, n, n))
+    V, G, _ = gpu_eval(ctx, t, f)
+    sel = []
+    for l in np.unique(t.level):
+        idx = np.flatnonzero(t.level == l)
+        sel += list(rng.choice(idx, min(len(idx), 3), replace=False))
+    sel = np.array(sorted(sel))
+    Vo, Gxo, Gyo = oracle.volume_at_nodes(t.level, t.ix, t.iy, f, leaves=sel)
+    ev = np.abs(V[0][sel] - Vo).max() / np.abs(V[0]).max()
+    ex = np.abs(G[0][sel, 0] - Gxo).max() / np.abs(G[0][:, 0]).max()
+    ey = np.abs(G[0][sel, 1] - Gyo).max() / np.abs(G[0][:, 1]).max()
+    print(f"n={n} p={p} flags={flags}: {len(sel)} leaves E(V)={ev:.2e} E(dV/dx1)={ex:.2e} E(dV/dx2)={ey:.2e}")
+    assert ev < tol and ex < tol and ey < tol
+
+
 def test_graph_replays_match_eager(ctx8):
     # The evaluation is captured once into a hipGraph and replayed; each replay,
     # with unrelated eager torch work and synchronisations in between and new
