@@ -341,7 +341,7 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
                 sd = split_slices(ctx->split, lv, ctx->split_tol, true);
       near_i8 = sv > 0 && sd > 0;   // otherwise more slices than the int8 kernel keeps: FP64
       tile_nsl[tt] = near_i8 ? sv | sd << 8 : 0;
-      if (near_i8) split_sf = std::max(split_sf, std::max(sv, sd));
+      if (near_i8) split_sf = std::max(split_sf, std::max(3, std::max(sv, sd)));   // the kernel uses at least 3
     }
     for (int c = 0; c < NCFG_U; ++c) {
       if (!(uni >> c & 1)) continue;

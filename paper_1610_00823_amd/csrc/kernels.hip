@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -356,7 +357,8 @@ __global__ void __launch_bounds__(256, 2) leaf_mfma_kernel(DevTables t, DevTree 
   __shared__ double sMass[LEAF_TILE];
   const int tile = g.unit_tile[blockIdx.x];
   if (tile < 0) return;                        // whole block: no barrier is skipped
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), col = lane & 15,
+            kq = lane >> 4;
   const int rhs = blockIdx.z, P = t.P, K2 = 2 * t.KP, MTR = 3 * P / 16;
   const int mtg = g.unit_mt[blockIdx.x] & 0xffff;   // first row tile of this unit
   const int ni = g.unit_mt[blockIdx.x] >> 16;       // row tiles per wave (<= TPW)
@@ -584,7 +586,6 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
                                                              const double *__restrict__ L, double *__restrict__ V,
                                                              double *__restrict__ G) {
   constexpr int SG = NEAR_SG, P = 64 * NCH, MTR = 3 * P / 16, PPT = SG * 256 / 512;
-  constexpr int SEQ[SG] = {0, 5, 1, 4, 2, 3};
   constexpr int KSC = KCF / 4, PERT = KCF / 8, SBF = KCF + 1;   // FP64 phase: chunks of KCF columns
   constexpr int BYTES_I8 = 2 * SG * 256 * 16, BYTES_F64 = 2 * LEAF_TILE * SBF * 8;
   __shared__ __attribute__((aligned(16))) unsigned char smem[BYTES_I8 > BYTES_F64 ? BYTES_I8 : BYTES_F64];
@@ -592,7 +593,8 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
   uint4(*sB)[SG * 256] = (uint4(*)[SG * 256])smem;
   const int tile = g.nunit_tile[blockIdx.x];
   if (tile < 0) return;                                    // whole block: no barrier is skipped
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, w4 = wave & 3, half = wave >> 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), w4 = wave & 3,
+            half = wave >> 2;
   const int col = lane & 15, kq = lane >> 4, rhs = blockIdx.z;
   const int mt0 = g.nunit_mt[blockIdx.x];
   const int NL = g.n_leaves, Sf = g.split_sf;
@@ -642,41 +644,54 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
       sB[buf][b * 256 + c * 4 + (kk ^ ((c >> 2) & 3))] = sok[m] ? stg[m] : make_uint4(0, 0, 0, 0);
     }
   };
-  i32x4 ar[3][TPW];
-  auto a_load = [&](int reg, int j, int a) {
+  // A fragments: a_cur for this iteration, a_nxt for the next, a_new two ahead
+  // (shifted each iteration, so the pipeline runs across items of any length)
+  i32x4 a_cur[TPW], a_nxt[TPW];
+  auto a_load = [&](i32x4 *dst, int j, int a) {
     const int sl = s0 + j / NCH, ch = j % NCH;
     const size_t base = (size_t)nslot_cfg[sl] * cfg_stride + (size_t)a * sl_stride + ch * 64;
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) ar[reg][i] = Atab[base + arow[i]];
+    for (int i = 0; i < TPW; ++i) dst[i] = Atab[base + arow[i]];
   };
 
-  if (nitems > 0) {
-    stage_load(0);
-    stage_write(0);
-    stage_load(nitems > 1 ? 1 : 0);
-    a_load(0, 0, SEQ[0]);
-    a_load(1, 0, SEQ[1]);
-  }
-  for (int j = 0; j < nitems; ++j) {
-    const int buf = j & 1, jn = j + 1 < nitems ? j + 1 : j, jnn = j + 2 < nitems ? j + 2 : jn;
-    __syncthreads();                                       // item j staged; buffer buf ^ 1 free
-    if (j + 1 < nitems) stage_write(buf ^ 1);
-    if (tid < 64 && j % NCH == 0) {                        // mass weights of this slot's sources
-      const int sl = s0 + j / NCH, src = nslot_src[sl * 64 + tid];
-      if (src >= 0) mU = fma(t.split_cfg_w2[nslot_cfg[sl]], lmass[(size_t)rhs * NL + src], mU);
+  // The slice counts are compile-time in the loop (one branch-free body per
+  // class, chosen once per block): T0 for row tile i = 0, T1 for i = 1, 2 (the
+  // two row types of a unit), each at least 3 and rounded up to T0 <= T1; extra
+  // slice pairs only make the product more exact.
+  const int T0 = Si[0] > 3 ? Si[0] : 3, T1r = Si[TPW - 1] > 3 ? Si[TPW - 1] : 3, T1 = T1r > T0 ? T1r : T0;
+  int Tsel[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) Tsel[i] = i == 0 ? T0 : T1;
+  auto run = [&](auto t0c, auto t1c) {
+    constexpr int C0 = decltype(t0c)::value, C1 = decltype(t1c)::value;
+    // iteration idx handles slice a = SEQ(idx): 0, C1-1, 1, C1-2, ... (long and short alternate)
+    auto seq = [](int idx) { return idx % 2 == 0 ? idx / 2 : C1 - 1 - idx / 2; };
+    if (nitems > 0) {
+      stage_load(0);
+      stage_write(0);
+      stage_load(nitems > 1 ? 1 : 0);
+      a_load(a_cur, 0, seq(0));
+      a_load(a_nxt, 0, seq(1));
     }
-    const uint4 *S = sB[buf];
+    for (int j = 0; j < nitems; ++j) {
+      const int buf = j & 1, jn = j + 1 < nitems ? j + 1 : j, jnn = j + 2 < nitems ? j + 2 : jn;
+      __syncthreads();                                     // item j staged; buffer buf ^ 1 free
+      if (j + 1 < nitems) stage_write(buf ^ 1);
+      if (tid < 64 && j % NCH == 0) {                      // mass weights of this slot's sources
+        const int sl = s0 + j / NCH, src = nslot_src[sl * 64 + tid];
+        if (src >= 0) mU = fma(t.split_cfg_w2[nslot_cfg[sl]], lmass[(size_t)rhs * NL + src], mU);
+      }
+      const uint4 *S = sB[buf];
 #pragma unroll
-    for (int idx = 0; idx < SG; ++idx) {
-      const int a = SEQ[idx];
-      // fragments two iterations ahead (the next item's first two at the end)
-      if (idx + 2 < SG) a_load((idx + 2) % 3, j, SEQ[idx + 2]);
-      else a_load((idx + 2) % 3, jn, SEQ[idx + 2 - SG]);
-      if (idx == 1) stage_load(jnn);
-      if (a < Smax) {
+      for (int idx = 0; idx < C1; ++idx) {
+        const int a = seq(idx);
+        // fragments two iterations ahead (the next item's first two at the end)
+        i32x4 a_new[TPW];
+        if (idx + 2 < C1) a_load(a_new, j, seq(idx + 2));
+        else a_load(a_new, jn, seq(idx + 2 - C1));
+        if (idx == 1) stage_load(jnn);
 #pragma unroll
-        for (int b = 0; b < SG - a; ++b) {
-          if (a + b >= Smax) break;
+        for (int b = 0; b < C1 - a; ++b) {
           i32x4 bv[2];
 #pragma unroll
           for (int nt = 0; nt < 2; ++nt) {
@@ -685,14 +700,31 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
           }
 #pragma unroll
           for (int i = 0; i < TPW; ++i)
-            if (a + b < Si[i]) {
+            if (a + b < (i == 0 ? C0 : C1)) {
 #pragma unroll
-              for (int nt = 0; nt < 2; ++nt) acc[i][nt][a + b] = mfma_i8(ar[idx % 3][i], bv[nt], acc[i][nt][a + b]);
+              for (int nt = 0; nt < 2; ++nt) acc[i][nt][a + b] = mfma_i8(a_cur[i], bv[nt], acc[i][nt][a + b]);
             }
+        }
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          a_cur[i] = a_nxt[i];
+          a_nxt[i] = a_new[i];
         }
       }
     }
+  };
+  using std::integral_constant;
+#define BX_RUN(A, B_) run(integral_constant<int, A>(), integral_constant<int, B_>())
+  if (T0 == 3) {
+    if (T1 == 3) BX_RUN(3, 3); else if (T1 == 4) BX_RUN(3, 4); else if (T1 == 5) BX_RUN(3, 5); else BX_RUN(3, 6);
+  } else if (T0 == 4) {
+    if (T1 == 4) BX_RUN(4, 4); else if (T1 == 5) BX_RUN(4, 5); else BX_RUN(4, 6);
+  } else if (T0 == 5) {
+    if (T1 == 5) BX_RUN(5, 5); else BX_RUN(5, 6);
+  } else {
+    BX_RUN(6, 6);
   }
+#undef BX_RUN
   // ---- FP64 phase: L2T, the W list and the U slots of tiles left in FP64,
   // seeded with the scaled int8 group sums.  The FP64 tables' rows are permuted
   // so that accumulator register r of a lane holds row 4 (lane / 16) + r, the
@@ -711,7 +743,7 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
         double v = 0.0;
 #pragma unroll
         for (int d = SG - 1; d >= 0; --d)
-          if (d < Si[i]) v += (double)acc[i][nt][d][r] * ldexp(rs, -7 * (d + 2));
+          if (d < Tsel[i]) v += (double)acc[i][nt][d][r] * ldexp(rs, -7 * (d + 2));
         fa[i][nt][r] = v;
       }
   }
