@@ -54,14 +54,29 @@ __global__ void __launch_bounds__(256) m2m_mfma_kernel(DevTables t, DevTree g, c
   dbl4 acc[MT];
 #pragma unroll
   for (int m = 0; m < MT; ++m) acc[m] = dbl4{0, 0, 0, 0};
-  for (int ks = 0; ks < KS; ks += 4) {
-    double bv[4];
+  if constexpr (KPT <= 32) {
+    // every operand requested at once: one memory round trip per level
+    double bv[KS], av[MT][KS];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bv[j] = ok ? bp[ks + j] : 0.0;
+    for (int ks = 0; ks < KS; ++ks) bv[ks] = bp[ks];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-      for (int m = 0; m < MT; ++m) acc[m] = mfma4(A[((size_t)m * KS + ks + j) * 64 + lane], bv[j], acc[m]);
+      for (int ks = 0; ks < KS; ++ks) av[m][ks] = A[((size_t)m * KS + ks) * 64 + lane];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int m = 0; m < MT; ++m) acc[m] = mfma4(av[m][ks], ok ? bv[ks] : 0.0, acc[m]);
+  } else {
+    for (int ks = 0; ks < KS; ks += 4) {
+      double bv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = bp[ks + j];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m] = mfma4(A[((size_t)m * KS + ks + j) * 64 + lane], ok ? bv[j] : 0.0, acc[m]);
+    }
   }
 #pragma unroll
   for (int m = 0; m < MT; ++m)
@@ -90,10 +105,16 @@ __global__ void __launch_bounds__(256) l2l_mfma_kernel(DevTables t, DevTree g, c
   double *Lr = L + (size_t)rhs * g.n_boxes * R;
   const double *bp = Lr + (size_t)box * R + kq * KS;
   const double *A = t.l2l_frag + (size_t)c * MT * KS * 64;
+  double bv[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) bv[ks] = bp[ks];      // the parent's expansion, one round trip
   for (int m = wave; m < MT; m += 4) {
+    double av[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) av[ks] = A[((size_t)m * KS + ks) * 64 + lane];
     dbl4 acc = dbl4{0, 0, 0, 0};
-#pragma unroll 4
-    for (int ks = 0; ks < KS; ++ks) acc = mfma4(A[((size_t)m * KS + ks) * 64 + lane], ok ? bp[ks] : 0.0, acc);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) acc = mfma4(av[ks], ok ? bv[ks] : 0.0, acc);
     if (ok) {
       double *Lc = Lr + (size_t)(g.child0[box] + c) * R;
 #pragma unroll
@@ -159,11 +180,21 @@ __global__ void __launch_bounds__(256) p2m_mfma_kernel(DevTables t, DevTree g, c
   const bool ok = leaf < g.n_leaves;
   const double *fp = f + ((size_t)rhs * g.n_leaves + (ok ? leaf : 0)) * t.P + kq * KS;
   dbl4 acc[MT];
-  for (int m = 0; m < MT; ++m) acc[m] = dbl4{0, 0, 0, 0};
-  for (int ks = 0; ks < KS; ++ks) {
-    const double b = ok ? fp[ks] : 0.0;
 #pragma unroll
-    for (int m = 0; m < MT; ++m) acc[m] = mfma4(t.p2m_frag[((size_t)m * KS + ks) * 64 + lane], b, acc[m]);
+  for (int m = 0; m < MT; ++m) acc[m] = dbl4{0, 0, 0, 0};
+  const double *A = t.p2m_frag;
+  for (int k0 = 0; k0 < KS; k0 += 4) {                  // KS = P/4 is a multiple of 4
+    double bv[4], av[MT][4];                           // 4 k-steps of operands requested at once
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bv[j] = fp[k0 + j];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) av[m][j] = A[((size_t)m * KS + k0 + j) * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int m = 0; m < MT; ++m) acc[m] = mfma4(av[m][j], ok ? bv[j] : 0.0, acc[m]);
   }
   if (!ok) return;
   const double h = box_h(g.width, g.leaf_level[leaf]), h2 = h * h;
@@ -599,7 +630,7 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
   const int mt0 = g.nunit_mt[blockIdx.x];
   const int NL = g.n_leaves, Sf = g.split_sf;
   const int s0 = g.nslot_ptr[tile], s1 = g.nslot_ptr[tile + 1], nitems = (s1 - s0) * NCH;
-  const int nsl = g.tile_nsl[tile], Sv = nsl & 255, Sd = (nsl >> 8) & 255, Smax = Sv > Sd ? Sv : Sd;
+  const int nsl = g.tile_nsl[tile], Sv = nsl & 255, Sd = (nsl >> 8) & 255;
   int Si[TPW];
   size_t arow[TPW];                                        // A offset of each row tile (in 16-byte units)
 #pragma unroll
