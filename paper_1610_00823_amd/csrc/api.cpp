@@ -1,6 +1,7 @@
 // C ABI of the box-code library: contexts, table build/upload, tree upload
 // and the stream-ordered evaluation of V and grad V.
 #include <algorithm>
+#include <unordered_map>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -433,6 +434,42 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
     xtile_ptr[tt + 1] = (int)xslot_cfg.size();
   }
   g.n_xtiles = nxt;
+  // M2L by sibling groups: for every internal box P, the 6 x 6 grid of boxes
+  // one level below P's 3 x 3 neighbourhood (children of P's colleagues), from
+  // which the V lists of P's four children are drawn; each V entry records the
+  // grid slot of its source.
+  std::vector<int> m2l_par, m2l_grid, v_slot(vs.size(), -1);
+  {
+    std::unordered_map<uint64_t, int> at;
+    for (int b = 0; b < H.n_boxes; ++b) at[box_key(H.lvl[b], H.bx[b], H.by[b])] = b;
+    for (int P = 0; P < H.n_boxes; ++P) {
+      if (H.child0[P] < 0) continue;
+      const int l = H.lvl[P];
+      m2l_par.push_back(P);
+      for (int i = 0; i < 36; ++i) m2l_grid.push_back(-1);
+      int *grid = &m2l_grid[m2l_grid.size() - 36];
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int64_t qx = (int64_t)H.bx[P] + dx, qy = (int64_t)H.by[P] + dy;
+          if (qx < 0 || qy < 0 || qx >= ((int64_t)1 << l) || qy >= ((int64_t)1 << l)) continue;
+          auto it = at.find(box_key(l, qx, qy));
+          if (it == at.end() || H.child0[it->second] < 0) continue;
+          for (int q = 0; q < 4; ++q) grid[(2 * (dy + 1) + (q >> 1)) * 6 + 2 * (dx + 1) + (q & 1)] = H.child0[it->second] + q;
+        }
+      for (int q = 0; q < 4; ++q) {   // the V entries of each child: their slots in this grid
+        const int tb = H.child0[P] + q;
+        for (int e = vp[tb]; e < vp[tb + 1]; ++e) {
+          const int src = vs[e], gx = H.bx[src] - (2 * H.bx[P] - 2), gy = H.by[src] - (2 * H.by[P] - 2);
+          if (gx < 0 || gx >= 6 || gy < 0 || gy >= 6 || grid[gy * 6 + gx] != src) {
+            bx_tree_destroy(t);
+            return fail(BX_E_INVALID_TREE, "bx_tree_upload: V-list source outside its parent's grid");
+          }
+          v_slot[e] = gy * 6 + gx;
+        }
+      }
+    }
+    g.n_m2l_par = (int)m2l_par.size();
+  }
   // internal boxes of each level (the M2M targets and the L2L sources)
   t->int_start.assign(H.n_levels + 1, 0);
   std::vector<int> ib;
@@ -459,7 +496,8 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       (rc = upload(t->dev, xs, &g.x_src, s)) || (rc = upload(t->dev, xc, &g.x_cfg, s)) ||
       (rc = upload(t->dev, xtile_box, &g.xtile_box, s)) || (rc = upload(t->dev, xtile_ptr, &g.xtile_ptr, s)) ||
       (rc = upload(t->dev, xslot_cfg, &g.xslot_cfg, s)) || (rc = upload(t->dev, xslot_src, &g.xslot_src, s)) ||
-      (rc = upload(t->dev, ib, &t->int_boxes, s)) ||
+      (rc = upload(t->dev, ib, &t->int_boxes, s)) || (rc = upload(t->dev, m2l_par, &g.m2l_par, s)) ||
+      (rc = upload(t->dev, m2l_grid, &g.m2l_grid, s)) || (rc = upload(t->dev, v_slot, &g.v_slot, s)) ||
       (rc = upload(t->dev, tile_tgt, &g.tile_tgt, s)) || (rc = upload(t->dev, tile_ptr, &g.tile_ptr, s)) ||
       (rc = upload(t->dev, slot_aoff, &g.slot_aoff, s)) || (rc = upload(t->dev, slot_type, &g.slot_type, s)) ||
       (rc = upload(t->dev, slot_op, &g.slot_op, s)) || (rc = upload(t->dev, tile_nsl, &g.tile_nsl, s)) ||

@@ -37,8 +37,13 @@ struct DevTree {
   const int *leaf_level;   // [NL]
   // U: per target leaf, CSR of (source leaf, config)
   const int *u_ptr, *u_src, *u_cfg;
-  // V: per target box, CSR of (source box, offset class)
-  const int *v_ptr, *v_src, *v_cfg;
+  // V: per target box, CSR of (source box, offset class, slot of the source in
+  // the 6 x 6 grid of its target's parent)
+  const int *v_ptr, *v_src, *v_cfg, *v_slot;
+  // M2L sibling groups: the internal boxes and their 6 x 6 grids (box or -1)
+  int n_m2l_par;
+  const int *m2l_par;      // [n_m2l_par]
+  const int *m2l_grid;     // [n_m2l_par][36]
   // W: per target leaf, CSR of (source box, config)
   const int *w_ptr, *w_src, *w_cfg;
   // X: per target box, CSR of (source leaf, config)

@@ -212,123 +212,138 @@ __global__ void __launch_bounds__(256) p2m_mfma_kernel(DevTables t, DevTree g, c
 // b~_l = sum_s (d/2)^-l [H y(s)]_l + [l = 0] sum_s a_0 (log h + log|d|),
 // y_k = a~_k (-d/2)^-k, for the V list of each box.  H (KP x KP, real, the same
 // for every offset) stays in registers as MFMA A fragments; the B columns are
-// (source, Re/Im) pairs, 8 sources per 16 columns.  One wave per target box;
-// the power tables of the 49 offsets sit in LDS, and the next 8 sources'
-// multipoles are loaded while the current ones are multiplied.  Writes
-// (initialises) every box's local expansion.
+// (source, Re/Im) pairs, 8 sources per 16 columns.  The V lists of the four
+// children of an internal box P (one wave each) all come from the 6 x 6 grid of
+// boxes below P's neighbourhood, whose multipoles are staged in LDS (rows
+// padded so that the 8 sources of a column group hit distinct banks).  Each
+// block keeps the power tables of the 49 offsets in LDS and works through a
+// contiguous range of parents, with the next parent's grid requested while the
+// current one is multiplied.  Writes (initialises) every box's local
+// expansion; the last block writes the root's zero expansion.
+constexpr int M2L_BLOCKS = 1024;
+
 template <int KPT>
 __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, const double *__restrict__ M,
-                                                       double *__restrict__ L) {
+                                                       double *__restrict__ L, int per_block) {
   constexpr int MT = KPT / 16, KS = KPT / 4;
-  constexpr int PWS = KPT + 1;                 // padded row: 8 offsets per column group, distinct banks
+  constexpr int PWS = KPT + 1;                 // padded rows: 8 offsets / sources per column group, distinct banks
+  constexpr int GPT = (36 * KPT + 255) / 256;  // grid coefficients per thread
   __shared__ double2 spw[2][NOFF_DEV * PWS];
+  __shared__ double2 sM[36 * PWS];
   __shared__ double slogd[NOFF_DEV];
+  const int rhs = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int col = lane & 15, kq = lane >> 4, part = col & 1;
+  const int nblk = gridDim.x - 1;
+  if ((int)blockIdx.x == nblk) {               // the root has no V list
+    double *Lb = L + (size_t)rhs * g.n_boxes * KPT * 2;
+    for (int i = threadIdx.x; i < 2 * KPT; i += 256) Lb[i] = 0.0;
+    return;
+  }
+  const int p0 = blockIdx.x * per_block;
+  const int p1 = p0 + per_block < g.n_m2l_par ? p0 + per_block : g.n_m2l_par;
+  if (p0 >= p1) return;                        // whole block: no barrier is skipped
+  const double *Mr = M + (size_t)rhs * g.n_boxes * KPT * 2;
   for (int i = threadIdx.x; i < NOFF_DEV * KPT; i += 256) {
     spw[0][i / KPT * PWS + i % KPT] = ((const double2 *)t.pw_src)[i];
     spw[1][i / KPT * PWS + i % KPT] = ((const double2 *)t.pw_tgt)[i];
   }
   if (threadIdx.x < NOFF_DEV) slogd[threadIdx.x] = t.logd[threadIdx.x];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4, part = col & 1;
-  const int box = blockIdx.x * 4 + wave;
-  if (box >= g.n_boxes) return;                 // no barrier follows
-  const int rhs = blockIdx.y;
-  const double *Mr = M + (size_t)rhs * g.n_boxes * KPT * 2;
   double hA[MT][KS];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) hA[m][ks] = t.H[(size_t)(m * 16 + col) * KPT + kq * KS + ks];
-  double acc[MT][4];
+  // this thread's share of a parent's grid: coefficient i = threadIdx.x + 256 j
+  double2 gm[GPT];
+  auto grid_load = [&](int pp) {
+    const int *grid = g.m2l_grid + (size_t)pp * 36;
 #pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[m][r] = 0.0;
-  double a0 = 0.0;
-  const double logh = log(box_h(g.width, g.lvl[box]));
-  const int e0 = g.v_ptr[box], e1 = g.v_ptr[box + 1];
-  // Two-stage pipeline over groups of 8 sources (this lane: source e + col/2):
-  // the data of group g+1 and the indices of group g+2 are requested before
-  // group g is multiplied.
-  auto idx = [&](int e, int &s_, int &o_, bool &ok_) {
-    const int pe = e + (col >> 1);
-    ok_ = pe < e1;
-    const int pc = ok_ ? pe : (e1 > 0 ? e1 - 1 : 0);   // always a valid entry: the loads are unconditional
-    s_ = g.v_src[pc];
-    o_ = g.v_cfg[pc];
-  };
-  auto data = [&](int s_, double2 *dst) {
-    const double2 *ap = (const double2 *)(Mr + (size_t)s_ * KPT * 2) + kq * KS;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) dst[ks] = ap[ks];
-  };
-  int s_c, o_c, s_n, o_n;
-  bool ok_c, ok_n;
-  double2 av[KS];
-  idx(e0, s_c, o_c, ok_c);
-  data(s_c, av);
-  idx(e0 + 8, s_n, o_n, ok_n);
-  for (int e = e0; e < e1; e += 8) {
-    double2 an[KS];
-    data(s_n, an);                                 // group g+1
-    int s_nn, o_nn;
-    bool ok_nn;
-    idx(e + 16, s_nn, o_nn, ok_nn);                // group g+2
-    double bv[KS];
-    const double2 *wp = &spw[0][o_c * PWS + kq * KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const double2 a = av[ks], w = wp[ks];
-      const double y = part ? a.x * w.y + a.y * w.x : a.x * w.x - a.y * w.y;
-      bv[ks] = ok_c ? y : 0.0;
+    for (int j = 0; j < GPT; ++j) {
+      const int i = threadIdx.x + 256 * j, sl = i < 36 * KPT ? i / KPT : 0;
+      const int gb = grid[sl];
+      gm[j] = ((const double2 *)(Mr + (size_t)(gb >= 0 ? gb : 0) * KPT * 2))[i % KPT];
+      if (gb < 0 || i >= 36 * KPT) gm[j] = double2{0, 0};
     }
-    a0 += (ok_c && part == 0 && kq == 0) ? av[0].x * (logh + slogd[o_c]) : 0.0;
-    dbl4 c[MT];
+  };
+  grid_load(p0);
+  for (int pp = p0; pp < p1; ++pp) {
+    __syncthreads();                           // the previous parent's grid is no longer read
 #pragma unroll
-    for (int m = 0; m < MT; ++m) c[m] = dbl4{0, 0, 0, 0};
+    for (int j = 0; j < GPT; ++j) {
+      const int i = threadIdx.x + 256 * j;
+      if (i < 36 * KPT) sM[i / KPT * PWS + i % KPT] = gm[j];
+    }
+    __syncthreads();
+    if (pp + 1 < p1) grid_load(pp + 1);        // in flight during this parent's products
+    const int box = g.child0[g.m2l_par[pp]] + wave;
+    double acc[MT][4];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-      for (int m = 0; m < MT; ++m) c[m] = mfma4(hA[m][ks], bv[ks], c[m]);
-    const double2 *qp = &spw[1][o_c * PWS];
+      for (int r = 0; r < 4; ++r) acc[m][r] = 0.0;
+    double a0 = 0.0;
+    const double logh = log(box_h(g.width, g.lvl[box]));
+    const int e0 = g.v_ptr[box], e1 = g.v_ptr[box + 1];
+    for (int e = e0; e < e1; e += 8) {
+      // this lane's source e + col/2 (a valid entry is read even past the end)
+      const int pe = e + (col >> 1);
+      const bool ok = pe < e1;
+      const int pc = ok ? pe : e1 - 1;
+      const int s_c = g.v_slot[pc], o_c = g.v_cfg[pc];
+      double bv[KS];
+      const double2 *ap = &sM[s_c * PWS + kq * KS];
+      const double2 *wp = &spw[0][o_c * PWS + kq * KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const double2 a = ap[ks], w = wp[ks];
+        const double y = part ? a.x * w.y + a.y * w.x : a.x * w.x - a.y * w.y;
+        bv[ks] = ok ? y : 0.0;
+      }
+      a0 += (ok && part == 0 && kq == 0) ? ap[0].x * (logh + slogd[o_c]) : 0.0;
+      dbl4 c[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) c[m] = dbl4{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) c[m] = mfma4(hA[m][ks], bv[ks], c[m]);
+      const double2 *qp = &spw[1][o_c * PWS];
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double z = c[m][r], zo = __shfl_xor(z, 1);
+          const double zr = part ? zo : z, zi = part ? z : zo;
+          const double2 q = qp[m * 16 + 4 * r + kq];
+          const double v = part ? zr * q.y + zi * q.x : zr * q.x - zi * q.y;
+          acc[m][r] += ok ? v : 0.0;
+        }
+    }
+    // sum over the 8 sources of each column group (lanes with equal kq and part)
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double z = c[m][r], zo = __shfl_xor(z, 1);
-        const double zr = part ? zo : z, zi = part ? z : zo;
-        const double2 q = qp[m * 16 + 4 * r + kq];
-        const double v = part ? zr * q.y + zi * q.x : zr * q.x - zi * q.y;
-        acc[m][r] += ok_c ? v : 0.0;
+        double v = acc[m][r];
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        acc[m][r] = v;
       }
+    a0 += __shfl_xor(a0, 2);
+    a0 += __shfl_xor(a0, 4);
+    a0 += __shfl_xor(a0, 8);
+    if (col < 2) {
+      double *Lb = L + ((size_t)rhs * g.n_boxes + box) * KPT * 2;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) av[ks] = an[ks];
-    s_c = s_n; o_c = o_n; ok_c = ok_n;
-    s_n = s_nn; o_n = o_nn; ok_n = ok_nn;
-  }
-  // sum over the 8 sources of each column group (lanes with equal kq and part)
+      for (int m = 0; m < MT; ++m)
 #pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      double v = acc[m][r];
-      v += __shfl_xor(v, 2);
-      v += __shfl_xor(v, 4);
-      v += __shfl_xor(v, 8);
-      acc[m][r] = v;
+        for (int r = 0; r < 4; ++r) {
+          const int l = m * 16 + 4 * r + kq;
+          Lb[2 * l + part] = acc[m][r] + (l == 0 && part == 0 ? a0 : 0.0);
+        }
     }
-  a0 += __shfl_xor(a0, 2);
-  a0 += __shfl_xor(a0, 4);
-  a0 += __shfl_xor(a0, 8);
-  if (col < 2) {
-    double *Lb = L + ((size_t)rhs * g.n_boxes + box) * KPT * 2;
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int l = m * 16 + 4 * r + kq;
-        Lb[2 * l + part] = acc[m][r] + (l == 0 && part == 0 ? a0 : 0.0);
-      }
   }
 }
 
@@ -913,10 +928,13 @@ void launch_m2m(const DevTables &t, const DevTree &g, const int *boxes, int nbox
   else hipLaunchKernelGGL(m2m_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
 }
 void launch_m2l(const DevTables &t, const DevTree &g, int nrhs, const double *M, double *L, hipStream_t s) {
-  dim3 grid((g.n_boxes + 3) / 4, nrhs);
-  if (t.KP == 16) hipLaunchKernelGGL(m2l_mfma_kernel<16>, grid, dim3(256), 0, s, t, g, M, L);
-  else if (t.KP == 32) hipLaunchKernelGGL(m2l_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, M, L);
-  else hipLaunchKernelGGL(m2l_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, M, L);
+  // blocks of contiguous parent ranges, plus one for the root
+  const int nb = g.n_m2l_par < M2L_BLOCKS ? (g.n_m2l_par > 0 ? g.n_m2l_par : 1) : M2L_BLOCKS;
+  const int per = g.n_m2l_par > 0 ? (g.n_m2l_par + nb - 1) / nb : 0;
+  dim3 grid(nb + 1, nrhs);
+  if (t.KP == 16) hipLaunchKernelGGL(m2l_mfma_kernel<16>, grid, dim3(256), 0, s, t, g, M, L, per);
+  else if (t.KP == 32) hipLaunchKernelGGL(m2l_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, M, L, per);
+  else hipLaunchKernelGGL(m2l_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, M, L, per);
 }
 void launch_p2l(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *L, hipStream_t s) {
   if (g.n_xtiles <= 0) return;
