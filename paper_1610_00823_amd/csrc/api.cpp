@@ -391,12 +391,27 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
   g.n_units = (int)unit_tile.size();
   if (split) {   // int8 near kernel: every tile (it writes V and G), 12 row tiles per block
     const int MTR = 3 * ctx->n * ctx->n / 16;
+    // a unit's cost: its int8 slice pairs and its FP64 slots (weighted 4 pairs:
+    // the weight that measured fastest; heavier weights split more tiles, and
+    // the split thirds repeat the B staging); tiles far above the balanced share
+    // of one resident block are split into thirds by rows (one row tile per wave)
+    auto cost_of = [&](int tt) {
+      const int sv = std::max(3, tile_nsl[tt] & 255), sd = std::max(3, tile_nsl[tt] >> 8);
+      const double pairs = (sv * (sv + 1) / 2.0 + 2.0 * sd * (sd + 1) / 2.0) / 3.0;
+      return 1.0 + (nslot_ptr[tt + 1] - nslot_ptr[tt]) * pairs + 4.0 * (tile_ptr[tt + 1] - tile_ptr[tt]);
+    };
+    double total = 0;
+    for (int tt = 0; tt < ntiles; ++tt) total += cost_of(tt) * (MTR / 12);
+    const double share = total / std::max(1, ctx->n_cu);
     std::vector<Unit> nu;
     for (int tt = 0; tt < ntiles; ++tt) {
-      const int sv = tile_nsl[tt] & 255, sd = tile_nsl[tt] >> 8;
-      const double pairs = (sv * (sv + 1) / 2.0 + 2.0 * sd * (sd + 1) / 2.0) / 3.0;
-      for (int mt0 = 0; mt0 < MTR; mt0 += 12)
-        nu.push_back({tt, mt0, 1.0 + (nslot_ptr[tt + 1] - nslot_ptr[tt]) * pairs});
+      const double c = cost_of(tt);
+      const bool heavy = c > 1.25 * share;
+      for (int mt0 = 0; mt0 < MTR; mt0 += 12) {
+        if (!heavy) nu.push_back({tt, mt0 | 3 << 16, c});
+        else
+          for (int j = 0; j < 3; ++j) nu.push_back({tt, (mt0 + 4 * j) | 1 << 16, c / 3 + 0.5});
+      }
     }
     order_units(nu, nunit_tile, nunit_mt);
   }

@@ -642,7 +642,8 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), w4 = wave & 3,
             half = wave >> 2;
   const int col = lane & 15, kq = lane >> 4, rhs = blockIdx.z;
-  const int mt0 = g.nunit_mt[blockIdx.x];
+  const int mt0 = g.nunit_mt[blockIdx.x] & 0xffff;         // first row tile of this unit
+  const int ni = g.nunit_mt[blockIdx.x] >> 16;             // row tiles per wave: TPW, or 1 for a heavy tile's thirds
   const int NL = g.n_leaves, Sf = g.split_sf;
   const int s0 = g.nslot_ptr[tile], s1 = g.nslot_ptr[tile + 1], nitems = (s1 - s0) * NCH;
   const int nsl = g.tile_nsl[tile], Sv = nsl & 255, Sd = (nsl >> 8) & 255;
@@ -651,13 +652,18 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
 #pragma unroll
   for (int i = 0; i < TPW; ++i) {
     const int mt = mt0 + w4 + 4 * i;
-    Si[i] = mt >= MTR ? 0 : (mt * 16 < P ? Sv : Sd);
-    arow[i] = (size_t)(mt < MTR ? mt : 0) * NCH * 64 + lane;
+    Si[i] = (i >= ni || mt >= MTR) ? 0 : (mt * 16 < P ? Sv : Sd);
+    arow[i] = (size_t)(i < ni && mt < MTR ? mt : mt0 + w4) * NCH * 64 + lane;
   }
   const int8_t *fr = fsl + (size_t)rhs * Sf * NL * P;
   const i32x4 *Atab = (const i32x4 *)t.near_i8;
-  const int *nslot_cfg = g.nslot_cfg, *nslot_src = g.nslot_src;
   const size_t cfg_stride = (size_t)NEAR_SMAX * MTR * NCH * 64, sl_stride = (size_t)MTR * NCH * 64;
+  // the tile's slot configurations and source leaves (at most 33 slots) in LDS:
+  // index reads in the loop then never wait behind the vector-memory queue
+  __shared__ int sCfg[33], sSrc[33 * 64];
+  for (int i = tid; i < (s1 - s0) * 64; i += 512) sSrc[i] = g.nslot_src[(size_t)s0 * 64 + i];
+  if (tid < s1 - s0) sCfg[tid] = g.nslot_cfg[s0 + tid];
+  __syncthreads();
 
   i32x4 acc[TPW][2][SG];
 #pragma unroll
@@ -673,11 +679,11 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
   uint4 stg[PPT];
   bool sok[PPT];
   auto stage_load = [&](int j) {
-    const int sl = s0 + j / NCH, ch = j % NCH;
+    const int sl = j / NCH, ch = j % NCH;
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
       const int q = tid + 512 * m, b = q >> 8, c = (q >> 2) & 63, kk = q & 3;
-      const int src = nslot_src[sl * 64 + c];
+      const int src = sSrc[sl * 64 + c];
       sok[m] = src >= 0;
       const int bb = b < Sf ? b : Sf - 1;
       stg[m] = *(const uint4 *)(fr + ((size_t)bb * NL + (src >= 0 ? src : 0)) * P + ch * 64 + kk * 16);
@@ -693,48 +699,46 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
   // A fragments: a_cur for this iteration, a_nxt for the next, a_new two ahead
   // (shifted each iteration, so the pipeline runs across items of any length)
   i32x4 a_cur[TPW], a_nxt[TPW];
-  auto a_load = [&](i32x4 *dst, int j, int a) {
-    const int sl = s0 + j / NCH, ch = j % NCH;
-    const size_t base = (size_t)nslot_cfg[sl] * cfg_stride + (size_t)a * sl_stride + ch * 64;
+  auto a_load = [&](i32x4 *dst, int j, int a, auto nic) {
+    constexpr int NI = decltype(nic)::value;
+    const int ch = j % NCH;
+    const size_t base = (size_t)sCfg[j / NCH] * cfg_stride + (size_t)a * sl_stride + ch * 64;
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) dst[i] = Atab[base + arow[i]];
+    for (int i = 0; i < NI; ++i) dst[i] = Atab[base + arow[i]];
   };
 
   // The slice counts are compile-time in the loop (one branch-free body per
   // class, chosen once per block): T0 for row tile i = 0, T1 for i = 1, 2 (the
   // two row types of a unit), each at least 3 and rounded up to T0 <= T1; extra
   // slice pairs only make the product more exact.
-  const int T0 = Si[0] > 3 ? Si[0] : 3, T1r = Si[TPW - 1] > 3 ? Si[TPW - 1] : 3, T1 = T1r > T0 ? T1r : T0;
+  const int T0 = Si[0] > 3 ? Si[0] : 3, T1r = Si[TPW - 1] > 3 ? Si[TPW - 1] : 3;
+  const int T1 = ni < TPW ? T0 : (T1r > T0 ? T1r : T0);
   int Tsel[TPW];
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) Tsel[i] = i == 0 ? T0 : T1;
-  auto run = [&](auto t0c, auto t1c) {
-    constexpr int C0 = decltype(t0c)::value, C1 = decltype(t1c)::value;
+  for (int i = 0; i < TPW; ++i) Tsel[i] = i >= ni ? 0 : (i == 0 ? T0 : T1);
+  auto run = [&](auto t0c, auto t1c, auto nic) {
+    constexpr int C0 = decltype(t0c)::value, C1 = decltype(t1c)::value, NI = decltype(nic)::value;
     // iteration idx handles slice a = SEQ(idx): 0, C1-1, 1, C1-2, ... (long and short alternate)
     auto seq = [](int idx) { return idx % 2 == 0 ? idx / 2 : C1 - 1 - idx / 2; };
     if (nitems > 0) {
       stage_load(0);
       stage_write(0);
       stage_load(nitems > 1 ? 1 : 0);
-      a_load(a_cur, 0, seq(0));
-      a_load(a_nxt, 0, seq(1));
+      a_load(a_cur, 0, seq(0), nic);
+      a_load(a_nxt, 0, seq(1), nic);
     }
     for (int j = 0; j < nitems; ++j) {
       const int buf = j & 1, jn = j + 1 < nitems ? j + 1 : j, jnn = j + 2 < nitems ? j + 2 : jn;
       __syncthreads();                                     // item j staged; buffer buf ^ 1 free
       if (j + 1 < nitems) stage_write(buf ^ 1);
-      if (tid < 64 && j % NCH == 0) {                      // mass weights of this slot's sources
-        const int sl = s0 + j / NCH, src = nslot_src[sl * 64 + tid];
-        if (src >= 0) mU = fma(t.split_cfg_w2[nslot_cfg[sl]], lmass[(size_t)rhs * NL + src], mU);
-      }
       const uint4 *S = sB[buf];
 #pragma unroll
       for (int idx = 0; idx < C1; ++idx) {
         const int a = seq(idx);
         // fragments two iterations ahead (the next item's first two at the end)
         i32x4 a_new[TPW];
-        if (idx + 2 < C1) a_load(a_new, j, seq(idx + 2));
-        else a_load(a_new, jn, seq(idx + 2 - C1));
+        if (idx + 2 < C1) a_load(a_new, j, seq(idx + 2), nic);
+        else a_load(a_new, jn, seq(idx + 2 - C1), nic);
         if (idx == 1) stage_load(jnn);
 #pragma unroll
         for (int b = 0; b < C1 - a; ++b) {
@@ -745,14 +749,14 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
             bv[nt] = __builtin_bit_cast(i32x4, S[b * 256 + c * 4 + (kq ^ ((c >> 2) & 3))]);
           }
 #pragma unroll
-          for (int i = 0; i < TPW; ++i)
+          for (int i = 0; i < NI; ++i)
             if (a + b < (i == 0 ? C0 : C1)) {
 #pragma unroll
               for (int nt = 0; nt < 2; ++nt) acc[i][nt][a + b] = mfma_i8(a_cur[i], bv[nt], acc[i][nt][a + b]);
             }
         }
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
+        for (int i = 0; i < NI; ++i) {
           a_cur[i] = a_nxt[i];
           a_nxt[i] = a_new[i];
         }
@@ -760,8 +764,11 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
     }
   };
   using std::integral_constant;
-#define BX_RUN(A, B_) run(integral_constant<int, A>(), integral_constant<int, B_>())
-  if (T0 == 3) {
+#define BX_RUN(A, B_) run(integral_constant<int, A>(), integral_constant<int, B_>(), integral_constant<int, TPW>())
+#define BX_RUN1(A) run(integral_constant<int, A>(), integral_constant<int, A>(), integral_constant<int, 1>())
+  if (ni < TPW) {                                          // one row tile per wave
+    if (T0 == 3) BX_RUN1(3); else if (T0 == 4) BX_RUN1(4); else if (T0 == 5) BX_RUN1(5); else BX_RUN1(6);
+  } else if (T0 == 3) {
     if (T1 == 3) BX_RUN(3, 3); else if (T1 == 4) BX_RUN(3, 4); else if (T1 == 5) BX_RUN(3, 5); else BX_RUN(3, 6);
   } else if (T0 == 4) {
     if (T1 == 4) BX_RUN(4, 4); else if (T1 == 5) BX_RUN(4, 5); else BX_RUN(4, 6);
@@ -770,7 +777,13 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
   } else {
     BX_RUN(6, 6);
   }
+#undef BX_RUN1
 #undef BX_RUN
+  if (tid < 64)                                            // mass weights of the sources of column tid
+    for (int sl = 0; sl < s1 - s0; ++sl) {
+      const int src = sSrc[sl * 64 + tid];
+      if (src >= 0) mU = fma(t.split_cfg_w2[sCfg[sl]], lmass[(size_t)rhs * NL + src], mU);
+    }
   // ---- FP64 phase: L2T, the W list and the U slots of tiles left in FP64,
   // seeded with the scaled int8 group sums.  The FP64 tables' rows are permuted
   // so that accumulator register r of a lane holds row 4 (lane / 16) + r, the
@@ -784,7 +797,7 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = (mt < MTR ? mt : 0) * 16 + 4 * kq + r;
+        const int row = (i < ni && mt < MTR ? mt : 0) * 16 + 4 * kq + r;
         const double rs = t.split_row_scale[row] * fsc;
         double v = 0.0;
 #pragma unroll
@@ -806,7 +819,9 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
   const int kmax = t.leaf_kmax;
   double mpart = 0.0;
   Regs<PERT> rb;
-  double an[2][TPW];
+  int ir[TPW];                                             // row tile offset of fragment i (tile 0 for i >= ni)
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) ir[i] = i < ni ? i : 0;
   auto f64_a = [&](int sl_, int c_) -> const double * {
     const int NC_ = (slot_type[sl_] == 0 ? P : K2) / KCF;
     return leaf_frag + slot_aoff[sl_] + ((size_t)(mt0 + w4) * NC_ + c_) * KSC * 64 + lane;
@@ -826,13 +841,14 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
   };
   int sl = f0, c = 0, buf = 0;
   __syncthreads();                                         // the int8 buffers are no longer read
+  double an[2][TPW];
   if (sl < f1) {
     const double *A0 = f64_a(sl, 0);
     const size_t st0 = f64_stride(sl);
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
-      for (int i = 0; i < TPW; ++i) an[jj][i] = A0[i * st0 + jj * 64];
+      for (int i = 0; i < TPW; ++i) an[jj][i] = A0[ir[i] * st0 + jj * 64];
     f64_b(sl, 0);
   }
   while (sl < f1) {
@@ -863,16 +879,17 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
       for (int i = 0; i < TPW; ++i) a[i] = an[ks % 2][i];
       if (ks + 2 < KSC) {
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) an[ks % 2][i] = Ac[i * stc + (ks + 2) * 64];
+        for (int i = 0; i < TPW; ++i) an[ks % 2][i] = Ac[ir[i] * stc + (ks + 2) * 64];
       } else if (more) {
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) an[ks % 2][i] = An[i * stn + (ks + 2 - KSC) * 64];
+        for (int i = 0; i < TPW; ++i) an[ks % 2][i] = An[ir[i] * stn + (ks + 2 - KSC) * 64];
       }
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt) {
         const double b = Sx[((2 * half + nt) * 16 + col) * SBF + kq * KSC + ks];
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) fa[i][nt] = mfma4(a[i], b, fa[i][nt]);
+        for (int i = 0; i < TPW; ++i)
+          if (i < ni) fa[i][nt] = mfma4(a[i], b, fa[i][nt]);
       }
     }
     sl = nsl;
@@ -900,7 +917,7 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int mt = mt0 + w4 + 4 * i;
-      if (mt >= MTR) continue;
+      if (i >= ni || mt >= MTR) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = mt * 16 + 4 * kq + r;
