@@ -195,6 +195,24 @@ int bx_table_copy(const bx_ctx *ctx, int which, double *out, int64_t cap, int64_
 int bx_split_tolerance(bx_ctx *ctx, double tol);
 
 /*
+ * The piecewise polynomial v~ of section 3.1 (the interpolant, on each leaf, of
+ * values computed at its collocation nodes) and likewise of the gradient, at
+ * arbitrary points.  Each target (x, y) is located in the tree (the leaf whose
+ * closed-open square [x0, x0 + h) x [y0, y0 + h) holds it; the root's right and
+ * top edges belong to the last leaves) and the tensor Chebyshev interpolant of
+ * that leaf's n x n values is evaluated (barycentric form, first-kind nodes).
+ *   V, G:    device, as written by bx_volume_eval_grad for n_rhs right-hand
+ *            sides; either may be NULL to skip it (not both).
+ *   xy:      device [n_targets][2] (x, y) in the tree's coordinates.
+ *   v_out:   device [n_rhs][n_targets] (needed iff V != NULL);
+ *   g_out:   device [n_rhs][n_targets][2] (needed iff G != NULL); caller-owned.
+ * Targets outside the root box get NaN.  Stream-ordered; no allocation.
+ * Errors: BX_E_ARG, BX_E_HIP.
+ */
+int bx_interpolate(const bx_ctx *ctx, const bx_tree *tree, const double *V, const double *G, int n_rhs,
+                   const double *xy, int64_t n_targets, double *v_out, double *g_out, bx_stream_t stream);
+
+/*
  * Per-phase timing with HIP events recorded on the evaluation stream.
  * bx_profile(ctx, 1) makes later evaluations record an event pair around each
  * phase; bx_profile_read waits for the recorded events, adds their elapsed

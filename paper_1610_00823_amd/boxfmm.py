@@ -28,6 +28,7 @@ TABLES = dict(near=0, p2m=1, m2m=2, l2l=3, m2l_core=4, m2l_src_pow=5, m2l_tgt_po
 PHASES = ["p2m", "m2m", "m2l", "p2l", "l2l", "leaf"]
 SYMBOLS = ["bx_create", "bx_build_tables", "bx_tree_upload", "bx_volume_eval_grad", "bx_volume_eval",
            "bx_volume_grad", "bx_query", "bx_tree_list", "bx_table_copy", "bx_split_tolerance", "bx_profile",
+           "bx_interpolate",
            "bx_profile_read",
            "bx_tree_destroy", "bx_destroy", "bx_last_error"]
 
@@ -63,6 +64,7 @@ def lib():
         L.bx_query.argtypes = [vp, vp, i32, ctypes.POINTER(dp)]
         L.bx_tree_list.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
         L.bx_table_copy.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
+        L.bx_interpolate.argtypes = [vp, vp, vp, vp, i32, vp, i64, vp, vp, vp]
         L.bx_split_tolerance.argtypes = [vp, dp]
         L.bx_profile.argtypes = [vp, i32]
         L.bx_profile_read.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(i32)]
@@ -213,6 +215,29 @@ def volume_eval_grad(ctx: Context, tree: Tree, f, V=None, G=None, stream=None):
                                      ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(G.data_ptr()),
                                      _stream_ptr(stream)))
     return V, G
+
+
+def interpolate(ctx: Context, tree: Tree, xy, V=None, G=None, stream=None):
+    """The per-leaf interpolants of V [n_rhs, N_L, n, n] and/or G [n_rhs, N_L, 2, n, n]
+    at points xy [m, 2] (torch, on the GPU): (v [n_rhs, m] or None, g [n_rhs, m, 2] or None)."""
+    import torch
+    if V is None and G is None:
+        raise ValueError("interpolate: give V or G")
+    ref = V if V is not None else G
+    nrhs, n, m = ref.shape[0], ctx.n, xy.shape[0]
+    _dev_check(xy, (m, 2), "xy")
+    if V is not None:
+        _dev_check(V, (nrhs, tree.n_leaves, n, n), "V")
+    if G is not None:
+        _dev_check(G, (nrhs, tree.n_leaves, 2, n, n), "G")
+    v = torch.empty((nrhs, m), dtype=torch.float64, device=xy.device) if V is not None else None
+    g = torch.empty((nrhs, m, 2), dtype=torch.float64, device=xy.device) if G is not None else None
+    if stream is None:
+        stream = torch.cuda.current_stream(xy.device)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+    _check(lib().bx_interpolate(ctx._h, tree._h, ptr(V), ptr(G), int(nrhs), ptr(xy), int(m), ptr(v), ptr(g),
+                                _stream_ptr(stream)))
+    return v, g
 
 
 def volume_eval(ctx, tree, f, V=None, stream=None):

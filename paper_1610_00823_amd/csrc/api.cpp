@@ -290,6 +290,7 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
   hipStream_t s = (hipStream_t)stream;
   DevTree &g = t->dg;
   g.n_leaves = H.n_leaves; g.n_boxes = H.n_boxes; g.n_levels = H.n_levels; g.width = H.width;
+  g.cx = H.cx; g.cy = H.cy;
   std::vector<int> leaf_level(H.n_leaves);
   for (int i = 0; i < H.n_leaves; ++i) leaf_level[i] = H.lvl[H.box_of_leaf[i]];
   std::vector<int> up, us, uc, vp, vs, vc, wp, ws, wc, xp, xs, xc;
@@ -696,6 +697,19 @@ int bx_volume_grad(bx_ctx *ctx, const bx_tree *tree, const double *f_dev, int n_
                    bx_stream_t stream) {
   if (!G_dev) return fail(BX_E_ARG, "bx_volume_grad: NULL output");
   return scratch_eval(ctx, tree, f_dev, n_rhs, nullptr, G_dev, false, stream);
+}
+
+int bx_interpolate(const bx_ctx *ctx, const bx_tree *tree, const double *V, const double *G, int n_rhs,
+                   const double *xy, int64_t n_targets, double *v_out, double *g_out, bx_stream_t stream) {
+  if (!ctx || !tree || !xy || n_rhs <= 0 || n_targets < 0 || (!V && !G) || (V && !v_out) || (G && !g_out))
+    return fail(BX_E_ARG, "bx_interpolate: NULL argument, n_rhs <= 0 or n_targets < 0");
+  if (!ctx->ready) return fail(BX_E_NO_TABLES, "bx_interpolate: bx_build_tables has not been called");
+  if (ctx->flags & BX_HOST_ONLY) return fail(BX_E_UNSUPPORTED, "bx_interpolate: host-only context");
+  if (tree->ctx != ctx) return fail(BX_E_ARG, "bx_interpolate: tree belongs to another context");
+  if (n_targets == 0) return BX_OK;
+  launch_interpolate(ctx->dt, tree->dg, V, G, n_rhs, xy, (long long)n_targets, v_out, g_out, (hipStream_t)stream);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BX_OK : hip_fail(e, "bx_interpolate");
 }
 
 int bx_split_tolerance(bx_ctx *ctx, double tol) {

@@ -28,7 +28,7 @@ struct DevTables {
 // Device copy of a tree's hierarchy and lists (CSR by target, sorted).
 struct DevTree {
   int n_leaves, n_boxes, n_levels;
-  double width;
+  double width, cx, cy;      // root width and centre
   const int *lvl;          // [NB]
   const int *child0;       // [NB]
   const int *parent;       // [NB]
@@ -104,5 +104,10 @@ void launch_split_prep(const DevTables &t, const DevTree &g, const double *f, in
 void launch_leaf_split(const DevTables &t, const DevTree &g, const int8_t *fsl, const double *lmass,
                        const double *fscale, const double *f, int nrhs, const double *M, const double *L, double *V,
                        double *G, hipStream_t s);
+
+// Interpolants of V and G (either may be null) at n_targets points xy [n][2]:
+// v_out [n_rhs][n], g_out [n_rhs][n][2]; NaN outside the root box.
+void launch_interpolate(const DevTables &t, const DevTree &g, const double *V, const double *G, int nrhs,
+                        const double *xy, long long n_targets, double *v_out, double *g_out, hipStream_t s);
 
 }  // namespace bx

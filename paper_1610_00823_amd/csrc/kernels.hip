@@ -928,6 +928,95 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
   }
 }
 
+// ------------------------------------------------- interpolation at points
+// One thread per (target, right-hand side): descend from the root to the leaf
+// holding the point, then evaluate the n x n tensor Chebyshev interpolant of
+// the leaf's values in barycentric form (first-kind nodes x_j = -cos((2j+1)pi/2n),
+// weights (-1)^j sin((2j+1)pi/2n); a coordinate on a node takes that node's
+// value exactly).
+template <int N>
+__device__ inline void cheb_basis(double u, double *l) {
+  double w[N], s = 0.0;
+  int hit = -1;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const double th = (2 * j + 1) * 3.14159265358979323846 / (2 * N);
+    const double xj = -cos(th), d = u - xj;
+    if (d == 0.0) hit = j;
+    w[j] = ((N - 1 - j) % 2 ? -1.0 : 1.0) * sin(th) / (d == 0.0 ? 1.0 : d);
+    s += w[j];
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) l[j] = hit >= 0 ? (j == hit ? 1.0 : 0.0) : w[j] / s;
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) interpolate_kernel(DevTree g, const double *__restrict__ V,
+                                                          const double *__restrict__ G, const double *__restrict__ xy,
+                                                          long long n_targets, double *__restrict__ v_out,
+                                                          double *__restrict__ g_out) {
+  constexpr int P = N * N;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_targets) return;
+  const int rhs = blockIdx.y;
+  const double x = xy[2 * i], y = xy[2 * i + 1];
+  // unit coordinates of the root square [0, 1)^2
+  double ux = (x - g.cx) / g.width + 0.5, uy = (y - g.cy) / g.width + 0.5;
+  int leaf = -1;
+  double lx = 0.0, ly = 0.0;                   // position inside the leaf, in [-1, 1]
+  if (ux >= 0.0 && ux <= 1.0 && uy >= 0.0 && uy <= 1.0) {
+    int box = 0;
+    double h = 1.0, x0 = 0.0, y0 = 0.0;
+    while (g.child0[box] >= 0) {               // children in Morton order (cx + 2 cy)
+      h *= 0.5;
+      const int qx = ux >= x0 + h ? 1 : 0, qy = uy >= y0 + h ? 1 : 0;
+      x0 += qx * h;
+      y0 += qy * h;
+      box = g.child0[box] + qx + 2 * qy;
+    }
+    leaf = g.leaf_of_box[box];
+    lx = 2.0 * (ux - x0) / h - 1.0;
+    ly = 2.0 * (uy - y0) / h - 1.0;
+    lx = lx > 1.0 ? 1.0 : lx;                  // the root's right and top edges
+    ly = ly > 1.0 ? 1.0 : ly;
+  }
+  if (leaf < 0) {
+    if (V) v_out[(long long)rhs * n_targets + i] = __builtin_nan("");
+    if (G) {
+      g_out[((long long)rhs * n_targets + i) * 2] = __builtin_nan("");
+      g_out[((long long)rhs * n_targets + i) * 2 + 1] = __builtin_nan("");
+    }
+    return;
+  }
+  double bx[N], by[N];
+  cheb_basis<N>(lx, bx);
+  cheb_basis<N>(ly, by);
+  if (V) {
+    const double *Vl = V + ((size_t)rhs * g.n_leaves + leaf) * P;
+    double v = 0.0;
+    for (int b = 0; b < N; ++b) {
+      double r = 0.0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) r = fma(bx[a], Vl[b * N + a], r);
+      v = fma(by[b], r, v);
+    }
+    v_out[(long long)rhs * n_targets + i] = v;
+  }
+  if (G) {
+    const double *Gl = G + ((size_t)rhs * g.n_leaves + leaf) * 2 * P;
+    for (int c = 0; c < 2; ++c) {
+      double v = 0.0;
+      for (int b = 0; b < N; ++b) {
+        double r = 0.0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) r = fma(bx[a], Gl[c * P + b * N + a], r);
+        v = fma(by[b], r, v);
+      }
+      g_out[((long long)rhs * n_targets + i) * 2 + c] = v;
+    }
+  }
+}
+
 }  // namespace
 
 void launch_p2m(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *M, hipStream_t s) {
@@ -1008,6 +1097,14 @@ void launch_leaf_split(const DevTables &t, const DevTree &g, const int8_t *fsl, 
   else if (t.leaf_kc == 64) BX_NEAR(4, 64);
   else BX_NEAR(4, 32);
 #undef BX_NEAR
+}
+
+void launch_interpolate(const DevTables &t, const DevTree &g, const double *V, const double *G, int nrhs,
+                        const double *xy, long long n_targets, double *v_out, double *g_out, hipStream_t s) {
+  const dim3 grid((unsigned)((n_targets + 255) / 256), nrhs);
+  if (t.n == 4) hipLaunchKernelGGL(interpolate_kernel<4>, grid, dim3(256), 0, s, g, V, G, xy, n_targets, v_out, g_out);
+  else if (t.n == 8) hipLaunchKernelGGL(interpolate_kernel<8>, grid, dim3(256), 0, s, g, V, G, xy, n_targets, v_out, g_out);
+  else hipLaunchKernelGGL(interpolate_kernel<16>, grid, dim3(256), 0, s, g, V, G, xy, n_targets, v_out, g_out);
 }
 
 }  // namespace bx

@@ -243,3 +243,78 @@ def test_split_multi_rhs_equals_single(ctx8s):
     for r in range(2):
         V1, G1 = B.volume_eval_grad(ctx8s, tr, torch.from_numpy(f[r].copy()).cuda())
         assert torch.equal(V1[0], V2[r]) and torch.equal(G1[0], G2[r])
+
+
+# ------------------------------------------------ interpolation at points
+def _locate(tree, x, y):
+    """Leaf holding (x, y) and its local coordinates in [-1, 1] (host reference)."""
+    ux, uy = (x - tree.cx) / tree.width + 0.5, (y - tree.cy) / tree.width + 0.5
+    for i in range(tree.n_leaves):
+        h = 0.5 ** tree.level[i]
+        x0, y0 = tree.ix[i] * h, tree.iy[i] * h
+        if x0 <= ux < x0 + h and y0 <= uy < y0 + h:
+            return i, 2 * (ux - x0) / h - 1, 2 * (uy - y0) / h - 1
+    raise AssertionError("point outside the tree")
+
+
+def test_interpolate_reproduces_nodes_and_numpy_chebyshev(ctx8):
+    # At the collocation nodes the interpolant returns the computed values; at
+    # random points it equals numpy's Chebyshev interpolant of the same values.
+    torch = _torch()
+    t = I.point_refined_tree([[0.3, 0.2], [-0.26, -0.4]], [5, 4])
+    rng = np.random.default_rng(31)
+    f = rng.standard_normal((t.n_leaves, 8, 8))
+    V, G, tr = gpu_eval(ctx8, t, f)
+    X, Y = oracle.leaf_nodes(t.level, t.ix, t.iy, 8)
+    sel = rng.choice(t.n_leaves, 20, replace=False)
+    xy = np.stack([X[sel].ravel(), Y[sel].ravel()], 1)
+    Vd, Gd = torch.from_numpy(V).cuda(), torch.from_numpy(G).cuda()
+    v, g = B.interpolate(ctx8, tr, torch.from_numpy(xy).cuda(), Vd, Gd)
+    v, g = v.cpu().numpy()[0], g.cpu().numpy()[0]
+    assert np.abs(v - V[0][sel].ravel()).max() < 1e-13 * np.abs(V).max()
+    assert np.abs(g[:, 0] - G[0][sel, 0].ravel()).max() < 1e-13 * np.abs(G).max()
+    assert np.abs(g[:, 1] - G[0][sel, 1].ravel()).max() < 1e-13 * np.abs(G).max()
+    pts = rng.uniform(-0.5, 0.5, size=(300, 2))
+    v, g = B.interpolate(ctx8, tr, torch.from_numpy(pts).cuda(), Vd, Gd)
+    v, g = v.cpu().numpy()[0], g.cpu().numpy()[0]
+    nodes = -np.cos((2 * np.arange(8) + 1) * np.pi / 16)
+    C = np.polynomial.chebyshev
+    for k, (x, y) in enumerate(pts):
+        leaf, lx, ly = _locate(t, x, y)
+        for vals, got in ((V[0][leaf], v[k]), (G[0][leaf, 0], g[k, 0]), (G[0][leaf, 1], g[k, 1])):
+            cx = C.chebfit(nodes, vals.T, 7)            # fit along x (columns), per y row
+            rows = C.chebval(lx, cx)                    # values at lx on each y node
+            ref = C.chebval(ly, C.chebfit(nodes, rows, 7))
+            assert abs(got - ref) < 1e-12 * max(1.0, np.abs(vals).max()), (k, got, ref)
+    out, _ = B.interpolate(ctx8, tr, torch.tensor([[0.7, 0.0], [0.0, -0.51]], dtype=torch.float64).cuda(), Vd)
+    assert torch.isnan(out).all()
+
+
+def test_interpolant_vs_oracle_off_node():
+    # v~ at points other than the nodes (section 3.1) against the oracle's V f~
+    # there.  The difference is the interpolation error of the smooth potential;
+    # its reference is the same interpolation applied to the exact radial
+    # Gaussian potential (closed form) at the nodes, compared with the closed
+    # form at the points.
+    torch = _torch()
+    ctx = B.Context(8, 30, B.BX_FP64)
+    t, src = I.workload("uniform4_gauss")
+    f = I.sample(t, src, 8)
+    V, G, tr = gpu_eval(ctx, t, f)
+    rng = np.random.default_rng(5)
+    pts = rng.uniform(-0.5, 0.5, size=(200, 2))
+    pd = torch.from_numpy(pts).cuda()
+    v, g = B.interpolate(ctx, tr, pd, torch.from_numpy(V).cuda(), torch.from_numpy(G).cuda())
+    Vo, Gxo, Gyo = oracle.volume(t.level, t.ix, t.iy, f, pts[:, 0], pts[:, 1])
+    ev = np.abs(v.cpu().numpy()[0] - Vo).max() / np.abs(V).max()
+    eg = np.abs(g.cpu().numpy()[0, :, 0] - Gxo).max() / np.abs(G[:, :, 0]).max()
+    X, Y = oracle.leaf_nodes(t.level, t.ix, t.iy, 8)
+    Ve, gxe, gye = CF.radial_gaussian(X, Y, 0.1)
+    Gn = np.stack([gxe, gye], 1)[None]
+    vi, gi = B.interpolate(ctx, tr, pd, torch.from_numpy(np.ascontiguousarray(Ve[None])).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(Gn)).cuda())
+    Vc, gxc, _ = CF.radial_gaussian(pts[:, 0], pts[:, 1], 0.1)
+    iv = np.abs(vi.cpu().numpy()[0] - Vc).max() / np.abs(Ve).max()
+    ig = np.abs(gi.cpu().numpy()[0, :, 0] - gxc).max() / np.abs(gxe).max()
+    print(f"off-node: E(v~)={ev:.2e} E(g~_1)={eg:.2e}; interpolation of the exact potential: {iv:.2e} {ig:.2e}")
+    assert ev < 2 * iv + 1e-12 and eg < 2 * ig + 1e-12
