@@ -276,8 +276,8 @@ def is_balanced(tree: Tree) -> bool:
 
 def workload(name: str, n: int = 8):
     """The named synthetic workloads: returns (tree, source function)."""
-    if name == "uniform4_gauss":
-        return uniform_tree(4), centred_gaussian(0.1)
+    if name.startswith("uniform") and name.endswith("_gauss"):   # uniform<depth>_gauss
+        return uniform_tree(int(name[len("uniform"):-len("_gauss")])), centred_gaussian(0.1)
     if name.startswith("gauss20"):
         seed = int(name.split("_s")[1]) if "_s" in name else 0
         src = random_gaussians(seed, 20)
