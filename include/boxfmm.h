@@ -103,9 +103,15 @@ typedef struct {
 /*
  * Validate a leaf set (it must tile the root exactly and be level-restricted,
  * section 3.1), build the box hierarchy and the interaction lists on the host,
- * and upload them.  Only n_trees == 1 is accepted.  The stream orders the
- * uploads.  Errors: BX_E_ARG, BX_E_INVALID_TREE, BX_E_NOT_BALANCED, BX_E_HIP,
- * BX_E_OOM.
+ * and upload them.  With n_trees > 1 the trees form a forest evaluated as one:
+ * each tree is validated and listed on its own (no interaction crosses trees),
+ * the leaves are numbered tree after tree in descriptor order (the layout of f,
+ * V and G), every level-synchronous pass covers all trees at that level, and
+ * one captured graph runs the whole forest.  The trees of a forest must share
+ * the root width (centres may differ); bx_interpolate takes single trees only.
+ * The stream orders the uploads.  Errors: BX_E_ARG, BX_E_INVALID_TREE (with the
+ * tree's index in the message), BX_E_NOT_BALANCED, BX_E_UNSUPPORTED (widths
+ * differ), BX_E_HIP, BX_E_OOM.
  */
 int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree **out,
                    bx_stream_t stream);

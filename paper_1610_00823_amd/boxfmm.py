@@ -156,6 +156,26 @@ class Tree:
     def from_inputs(cls, ctx, tree, stream=None):
         return cls(ctx, tree.level, tree.ix, tree.iy, tree.cx, tree.cy, tree.width, stream)
 
+    @classmethod
+    def forest(cls, ctx, trees, stream=None):
+        """One bx_tree of several trees (objects with level, ix, iy, cx, cy, width):
+        leaves numbered tree after tree; the trees must share the root width."""
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self._keep = []
+        descs = (_TreeDesc * len(trees))()
+        for k, t in enumerate(trees):
+            lv = np.ascontiguousarray(t.level, np.int8)
+            ix = np.ascontiguousarray(t.ix, np.int32)
+            iy = np.ascontiguousarray(t.iy, np.int32)
+            self._keep += [lv, ix, iy]
+            descs[k] = _TreeDesc(float(t.cx), float(t.cy), float(t.width), int(lv.size), lv.ctypes.data,
+                                 ix.ctypes.data, iy.ctypes.data)
+        self._h = ctypes.c_void_p()
+        _check(lib().bx_tree_upload(ctx._h, descs, len(trees), ctypes.byref(self._h), _stream_ptr(stream)))
+        self.n_leaves = int(sum(np.asarray(t.level).size for t in trees))
+        return self
+
     def query(self, what: str) -> float:
         v = ctypes.c_double()
         _check(lib().bx_query(self.ctx._h, self._h, Q[what], ctypes.byref(v)))

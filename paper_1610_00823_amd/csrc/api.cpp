@@ -53,6 +53,8 @@ struct bx_tree {
   int exp_rhs = 0;
   double upload_ms = 0.0;
   int64_t n_slots = 0;
+  int n_trees = 1;
+  std::vector<int> box_tree;           // tree of each box (forests)
 };
 
 namespace bx {
@@ -275,13 +277,25 @@ void leaf_units(const std::vector<int> &tile_ptr, int n, int blocks_per_cu, int 
 int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree **out, bx_stream_t stream) {
   if (!ctx || !trees || !out) return fail(BX_E_ARG, "bx_tree_upload: NULL argument");
   *out = nullptr;
-  if (n_trees != 1) return fail(BX_E_UNSUPPORTED, "bx_tree_upload: one tree per call");
+  if (n_trees < 1) return fail(BX_E_ARG, "bx_tree_upload: n_trees < 1");
   auto t0 = std::chrono::steady_clock::now();
   bx_tree *t = new (std::nothrow) bx_tree;
   if (!t) return fail(BX_E_OOM, "bx_tree_upload");
   t->ctx = ctx;
+  t->n_trees = n_trees;
   std::string err;
-  int rc = build_tree(t->H, trees[0], err);
+  int rc = BX_OK;
+  if (n_trees == 1) {
+    rc = build_tree(t->H, trees[0], err);
+    t->box_tree.assign(t->H.n_boxes, 0);
+  } else {   // a forest: each tree validated and listed on its own, then merged
+    std::vector<HostTree> parts(n_trees);
+    for (int k = 0; k < n_trees && !rc; ++k) {
+      rc = build_tree(parts[k], trees[k], err);
+      if (rc) err = "tree " + std::to_string(k) + ": " + err;
+    }
+    if (!rc) rc = merge_forest(parts, t->H, t->box_tree, err);
+  }
   if (rc) {
     delete t;
     return fail(rc, "bx_tree_upload: " + err);
@@ -291,6 +305,7 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
   DevTree &g = t->dg;
   g.n_leaves = H.n_leaves; g.n_boxes = H.n_boxes; g.n_levels = H.n_levels; g.width = H.width;
   g.cx = H.cx; g.cy = H.cy;
+  g.n_roots = H.n_levels > 0 ? H.level_start[1] : 0;
   std::vector<int> leaf_level(H.n_leaves);
   for (int i = 0; i < H.n_leaves; ++i) leaf_level[i] = H.lvl[H.box_of_leaf[i]];
   std::vector<int> up, us, uc, vp, vs, vc, wp, ws, wc, xp, xs, xc;
@@ -456,12 +471,13 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
   // grid slot of its source.
   std::vector<int> m2l_par, m2l_grid, v_slot(vs.size(), -1);
   {
-    std::unordered_map<uint64_t, int> at;
-    for (int b = 0; b < H.n_boxes; ++b) at[box_key(H.lvl[b], H.bx[b], H.by[b])] = b;
+    std::vector<std::unordered_map<uint64_t, int>> at_tree(t->n_trees);   // per tree: key -> box
+    for (int b = 0; b < H.n_boxes; ++b) at_tree[t->box_tree[b]][box_key(H.lvl[b], H.bx[b], H.by[b])] = b;
     for (int P = 0; P < H.n_boxes; ++P) {
       if (H.child0[P] < 0) continue;
       const int l = H.lvl[P];
       m2l_par.push_back(P);
+      const std::unordered_map<uint64_t, int> &at = at_tree[t->box_tree[P]];
       for (int i = 0; i < 36; ++i) m2l_grid.push_back(-1);
       int *grid = &m2l_grid[m2l_grid.size() - 36];
       for (int dy = -1; dy <= 1; ++dy)
@@ -706,6 +722,7 @@ int bx_interpolate(const bx_ctx *ctx, const bx_tree *tree, const double *V, cons
   if (!ctx->ready) return fail(BX_E_NO_TABLES, "bx_interpolate: bx_build_tables has not been called");
   if (ctx->flags & BX_HOST_ONLY) return fail(BX_E_UNSUPPORTED, "bx_interpolate: host-only context");
   if (tree->ctx != ctx) return fail(BX_E_ARG, "bx_interpolate: tree belongs to another context");
+  if (tree->n_trees != 1) return fail(BX_E_UNSUPPORTED, "bx_interpolate: one tree, not a forest");
   if (n_targets == 0) return BX_OK;
   launch_interpolate(ctx->dt, tree->dg, V, G, n_rhs, xy, (long long)n_targets, v_out, g_out, (hipStream_t)stream);
   hipError_t e = hipGetLastError();

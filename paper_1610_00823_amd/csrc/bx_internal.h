@@ -109,6 +109,9 @@ struct HostTree {
 };
 
 int build_tree(HostTree &T, const bx_tree_desc &d, std::string &err);
+// Several trees as one structure (level-major boxes, leaves tree after tree);
+// box_tree[b] receives the tree of each merged box.
+int merge_forest(const std::vector<HostTree> &parts, HostTree &T, std::vector<int> &box_tree, std::string &err);
 
 void set_error(const std::string &msg);
 

@@ -28,7 +28,8 @@ struct DevTables {
 // Device copy of a tree's hierarchy and lists (CSR by target, sorted).
 struct DevTree {
   int n_leaves, n_boxes, n_levels;
-  double width, cx, cy;      // root width and centre
+  double width, cx, cy;      // root width and centre (of the first tree of a forest)
+  int n_roots;               // level-0 boxes: 1, or the trees of a forest
   const int *lvl;          // [NB]
   const int *child0;       // [NB]
   const int *parent;       // [NB]

@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256) p2m_mfma_kernel(DevTables t, DevTree g, c
 // block keeps the power tables of the 49 offsets in LDS and works through a
 // contiguous range of parents, with the next parent's grid requested while the
 // current one is multiplied.  Writes (initialises) every box's local
-// expansion; the last block writes the root's zero expansion.
+// expansion; the last block writes the roots' zero expansions.
 constexpr int M2L_BLOCKS = 1024;
 
 template <int KPT>
@@ -235,9 +235,9 @@ __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, c
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int col = lane & 15, kq = lane >> 4, part = col & 1;
   const int nblk = gridDim.x - 1;
-  if ((int)blockIdx.x == nblk) {               // the root has no V list
+  if ((int)blockIdx.x == nblk) {               // the roots (level-0 boxes first) have no V list
     double *Lb = L + (size_t)rhs * g.n_boxes * KPT * 2;
-    for (int i = threadIdx.x; i < 2 * KPT; i += 256) Lb[i] = 0.0;
+    for (int i = threadIdx.x; i < 2 * KPT * g.n_roots; i += 256) Lb[i] = 0.0;
     return;
   }
   const int p0 = blockIdx.x * per_block;

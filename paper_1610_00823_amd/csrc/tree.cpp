@@ -254,4 +254,70 @@ int build_tree(HostTree &T, const bx_tree_desc &d, std::string &err) {
   return BX_OK;
 }
 
+// A forest as one tree structure: boxes level-major (all trees' level-l boxes
+// together, tree after tree, each in its own order, so children stay
+// contiguous), leaves in descriptor order tree after tree, every list index
+// offset into the merged numbering.  The trees must share the root width (the
+// operators depend on the box widths); their interaction lists never meet.
+int merge_forest(const std::vector<HostTree> &P, HostTree &T, std::vector<int> &box_tree, std::string &err) {
+  T = HostTree();
+  T.width = P[0].width;
+  T.cx = P[0].cx;
+  T.cy = P[0].cy;
+  const int K = (int)P.size();
+  std::vector<int> leaf_off(K + 1, 0);
+  for (int k = 0; k < K; ++k) {
+    if (P[k].width != T.width) {
+      err = "trees of a forest must share the root width";
+      return BX_E_UNSUPPORTED;
+    }
+    T.n_levels = std::max(T.n_levels, P[k].n_levels);
+    leaf_off[k + 1] = leaf_off[k] + P[k].n_leaves;
+  }
+  T.n_leaves = leaf_off[K];
+  std::vector<std::vector<int>> gid(K);
+  for (int k = 0; k < K; ++k) gid[k].assign(P[k].n_boxes, -1);
+  T.level_start.assign(T.n_levels + 1, 0);
+  int nb = 0;
+  for (int l = 0; l < T.n_levels; ++l) {
+    T.level_start[l] = nb;
+    for (int k = 0; k < K; ++k)
+      if (l < P[k].n_levels)
+        for (int b = P[k].level_start[l]; b < P[k].level_start[l + 1]; ++b) gid[k][b] = nb++;
+  }
+  T.level_start[T.n_levels] = nb;
+  T.n_boxes = nb;
+  T.lvl.assign(nb, 0); T.bx.assign(nb, 0); T.by.assign(nb, 0);
+  T.parent.assign(nb, -1); T.child0.assign(nb, -1); T.leaf_of_box.assign(nb, -1);
+  T.box_of_leaf.assign(T.n_leaves, -1);
+  box_tree.assign(nb, 0);
+  for (int k = 0; k < K; ++k) {
+    const HostTree &Q = P[k];
+    for (int b = 0; b < Q.n_boxes; ++b) {
+      const int g = gid[k][b];
+      T.lvl[g] = Q.lvl[b]; T.bx[g] = Q.bx[b]; T.by[g] = Q.by[b];
+      T.parent[g] = Q.parent[b] >= 0 ? gid[k][Q.parent[b]] : -1;
+      T.child0[g] = Q.child0[b] >= 0 ? gid[k][Q.child0[b]] : -1;
+      T.leaf_of_box[g] = Q.leaf_of_box[b] >= 0 ? leaf_off[k] + Q.leaf_of_box[b] : -1;
+      box_tree[g] = k;
+    }
+    for (int i = 0; i < Q.n_leaves; ++i) T.box_of_leaf[leaf_off[k] + i] = gid[k][Q.box_of_leaf[i]];
+    auto leaf = [&](int i) { return leaf_off[k] + i; };
+    auto box = [&](int b) { return gid[k][b]; };
+    for (size_t e = 0; e < Q.u_t.size(); ++e) {
+      T.u_t.push_back(leaf(Q.u_t[e])); T.u_s.push_back(leaf(Q.u_s[e])); T.u_c.push_back(Q.u_c[e]);
+    }
+    for (size_t e = 0; e < Q.v_t.size(); ++e) {
+      T.v_t.push_back(box(Q.v_t[e])); T.v_s.push_back(box(Q.v_s[e])); T.v_c.push_back(Q.v_c[e]);
+    }
+    for (size_t e = 0; e < Q.w_t.size(); ++e) {
+      T.w_t.push_back(leaf(Q.w_t[e])); T.w_s.push_back(box(Q.w_s[e])); T.w_c.push_back(Q.w_c[e]);
+    }
+    for (size_t e = 0; e < Q.x_t.size(); ++e) {
+      T.x_t.push_back(box(Q.x_t[e])); T.x_s.push_back(leaf(Q.x_s[e])); T.x_c.push_back(Q.x_c[e]);
+    }
+  }
+  return BX_OK;
+}
+
 }  // namespace bx

@@ -318,3 +318,36 @@ def test_interpolant_vs_oracle_off_node():
     ig = np.abs(gi.cpu().numpy()[0, :, 0] - gxc).max() / np.abs(gxe).max()
     print(f"off-node: E(v~)={ev:.2e} E(g~_1)={eg:.2e}; interpolation of the exact potential: {iv:.2e} {ig:.2e}")
     assert ev < 2 * iv + 1e-12 and eg < 2 * ig + 1e-12
+
+
+# ----------------------------------------------------------------- forests
+def _forest_inputs(n, seed):
+    trees = [I.point_refined_tree([[0.3, 0.2]], [5]), I.uniform_tree(3),
+             I.point_refined_tree([[-0.3, 0.4], [0.1, -0.2]], [4, 6]), I.uniform_tree(1)]
+    rng = np.random.default_rng(seed)
+    fs = [rng.standard_normal((2, t.n_leaves, n, n)) for t in trees]
+    return trees, fs
+
+
+@pytest.mark.parametrize("flags", [B.BX_FP64, B.BX_SPLIT_INT8], ids=["fp64", "split"])
+def test_forest_equals_separate_trees(ctx8, flags):
+    # Four trees of uneven depth and two right-hand sides as one forest (one
+    # upload, one captured evaluation) against each tree evaluated alone in FP64.
+    torch = _torch()
+    trees, fs = _forest_inputs(8, 41)
+    ctx = ctx8 if flags == B.BX_FP64 else B.Context(8, 30, flags)
+    forest = B.Tree.forest(ctx, trees)
+    f = np.concatenate(fs, axis=1)
+    V, G = B.volume_eval_grad(ctx, forest, torch.from_numpy(f).cuda())
+    V, G = V.cpu().numpy(), G.cpu().numpy()
+    off = 0
+    for t, ft in zip(trees, fs):
+        tr = B.Tree.from_inputs(ctx8, t)
+        Vs, Gs = B.volume_eval_grad(ctx8, tr, torch.from_numpy(ft).cuda())
+        Vs, Gs = Vs.cpu().numpy(), Gs.cpu().numpy()
+        sl = slice(off, off + t.n_leaves)
+        ev, eg = E(V[:, sl], Vs), E(G[:, sl], Gs)
+        tol = 1e-13 if flags == B.BX_FP64 else 1e-10
+        print(f"tree with {t.n_leaves} leaves: E(V)={ev:.2e} E(G)={eg:.2e}")
+        assert ev < tol and eg < tol
+        off += t.n_leaves

@@ -369,3 +369,47 @@ def test_split_error_bound_holds():
     for k in (0, 1):
         ratio = err[k, 3:7] / err[k, 4:8]
         assert np.all(ratio > 50) and np.all(ratio < 300)
+
+
+def test_forest_lists_are_the_union_of_the_trees():
+    # A forest's lists are each tree's lists with the leaf numbering offset
+    # tree after tree (U list: (target leaf, source leaf, config)); nothing
+    # crosses trees.
+    ctx = B.Context(8, 16, B.BX_FP64 | B.BX_HOST_ONLY)
+    trees = [I.point_refined_tree([[0.3, 0.2]], [5]), I.uniform_tree(2),
+             I.point_refined_tree([[-0.3, 0.4], [0.1, -0.2]], [4, 6])]
+    forest = B.Tree.forest(ctx, trees)
+    off = 0
+    expect = {k: [] for k in range(4)}
+    for t in trees:
+        tr = B.Tree.from_inputs(ctx, t)
+        for k in (0, 2):
+            L = tr.lists(k).copy()
+            L[:, 0] += off
+            if k == 0:
+                L[:, 1] += off
+            expect[k].append(L)
+        for k in (1, 3):
+            expect[k].append(tr.lists(k))
+        off += t.n_leaves
+    assert forest.n_leaves == off
+    U = forest.lists(0)
+    assert sorted(map(tuple, U)) == sorted(map(tuple, np.concatenate(expect[0])))
+    for k in (1, 2, 3):
+        assert len(forest.lists(k)) == sum(len(a) for a in expect[k])
+    assert forest.query("n_levels") == max(B.Tree.from_inputs(ctx, t).query("n_levels") for t in trees)
+
+
+def test_forest_errors():
+    ctx = B.Context(8, 16, B.BX_FP64 | B.BX_HOST_ONLY)
+    a, b = I.uniform_tree(2), I.uniform_tree(3)
+    b.width = 2.0
+    with pytest.raises(B.BoxFMMError) as e:
+        B.Tree.forest(ctx, [a, b])
+    assert e.value.code == B.BX_E_UNSUPPORTED
+    bad = I.uniform_tree(2)
+    bad.level = bad.level.copy()
+    bad.level[0] = 3                                  # leaves no longer tile the root
+    with pytest.raises(B.BoxFMMError) as e:
+        B.Tree.forest(ctx, [a, bad])
+    assert e.value.code == B.BX_E_INVALID_TREE and "tree 1" in str(e.value)
