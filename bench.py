@@ -95,11 +95,19 @@ def run_precision(args, precision, tree, f_host):
     ctx = B.Context(args.n, args.p, flags)
     t_tables = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
-    tr = B.Tree.from_inputs(ctx, tree, stream)
-    f = torch.from_numpy(f_host).cuda().unsqueeze(0)
+    tr = B.Tree.forest(ctx, tree.trees, stream) if isinstance(tree, Forest) else B.Tree.from_inputs(ctx, tree, stream)
+    f = torch.from_numpy(f_host).cuda()
+    if f.dim() == 3:
+        f = f.unsqueeze(0)
     V = torch.empty_like(f)
-    G = torch.empty((1, tree.n_leaves, 2, args.n, args.n), dtype=torch.float64, device=f.device)
+    G = torch.empty((f.shape[0], tree.n_leaves, 2, args.n, args.n), dtype=torch.float64, device=f.device)
     log(f"{precision}: tables {t_tables:.1f} s, tree upload {tr.query('upload_ms'):.0f} ms")
+    tuning = None
+    if args.autotune:                    # untimed set-up, like the tables and the upload
+        t0 = time.perf_counter()
+        _, _, tuning = B.autotune(ctx, tr, f, V, G, reps=3, stream=stream)
+        log(f"{precision}: autotune {time.perf_counter() - t0:.1f} s: heavy {tuning[0]}, fp64 weight "
+            f"{tuning[1]}, m2l blocks {tuning[2]}, {tuning[3]:.4f} ms")
     for _ in range(args.warmup):
         B.volume_eval_grad(ctx, tr, f, V, G, stream)
     torch.cuda.synchronize()
@@ -118,13 +126,14 @@ def run_precision(args, precision, tree, f_host):
     ctx.profile(False)
     phase_ms, nev = ctx.profile_read()
     per_eval = {k: v / max(nev, 1) for k, v in phase_ms.items()}
+    nr = int(f.shape[0])
     phases = {}
     for k, v in per_eval.items():
         a, _ = tr.phase_cost(k)
-        phases[k] = {"ms": round(v, 4), "tflops": round(a / (v / 1e3) / 1e12, 3) if v > 0 else None}
-    npts = tree.n_leaves * args.n * args.n
-    return {"ctx": ctx, "tree": tr, "V": V, "G": G, "ms_step": ms_step, "ms_prof": ms_prof,
-            "value": npts / (ms_step / 1e3), "per_eval": per_eval, "phases": phases, "t_tables": t_tables,
+        phases[k] = {"ms": round(v, 4), "tflops": round(nr * a / (v / 1e3) / 1e12, 3) if v > 0 else None}
+    npts = f_host.size
+    return {"nrhs": nr, "ctx": ctx, "tree": tr, "V": V, "G": G, "ms_step": ms_step, "ms_prof": ms_prof,
+            "value": npts / (ms_step / 1e3), "per_eval": per_eval, "tuning": tr.tuning(), "phases": phases, "t_tables": t_tables,
             "split_products": tr.query("split_products") if precision == "split" else None}
 
 
@@ -132,6 +141,7 @@ def roofline_of(res, args, precision):
     per_eval = res["per_eval"]
     dom = max(per_eval, key=per_eval.get)
     fl, by = res["tree"].phase_cost(dom)
+    fl, by = fl * res["nrhs"], by * res["nrhs"]
     bound, peak = BOUND[dom]
     t_dom = per_eval[dom] / 1e3
     if bound == "hbm":
@@ -144,6 +154,14 @@ def roofline_of(res, args, precision):
     return {"bound": bound, "achieved": ach, "peak": pk, "unit": unit, "frac": ach / pk,
             "traffic": measured_traffic(kernel, args.workload, precision), "kernel": kernel, "phase": dom,
             "launch_ms": per_eval[dom], "algorithmic_flops": fl, "algorithmic_bytes": by}
+
+
+class Forest:
+    """Several trees evaluated as one (the leaves tree after tree)."""
+
+    def __init__(self, trees):
+        self.trees = trees
+        self.n_leaves = sum(t.n_leaves for t in trees)
 
 
 def rel_err(a, b):
@@ -161,7 +179,10 @@ def main():
     ap.add_argument("--precision", choices=["both", "fp64", "split"], default="both",
                     help="both: the mixed (int8-split near tables) path is the headline, with the plain FP64 "
                          "path beside it")
+    ap.add_argument("--nrhs", type=int, default=1, help="right-hand sides on the same tree (seeded sources)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time candidate schedules of each tree before the timed region and keep the fastest")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized FP64 buffer on the GPU 5 times (a plain copy kernel "
                          "of known traffic, to scale the FETCH_SIZE / WRITE_SIZE counters)")
@@ -186,9 +207,15 @@ def main():
 
     t0 = time.perf_counter()
     tree, src = I.workload(args.workload, args.n)
-    f_host = I.sample(tree, src, args.n)
+    if isinstance(tree, list):                       # a forest: one upload, one evaluation
+        f_host = np.concatenate([I.sample(t, s_, args.n) for t, s_ in zip(tree, src)])
+        tree = Forest(tree)
+    elif args.nrhs > 1:                              # the same tree, n_rhs seeded sources
+        f_host = np.stack([I.sample(tree, I.random_gaussians(1000 + r, 20), args.n) for r in range(args.nrhs)])
+    else:
+        f_host = I.sample(tree, src, args.n)
     log(f"inputs: {args.workload}: {tree.n_leaves} leaves, {f_host.size} points, {time.perf_counter() - t0:.1f} s")
-    npts = tree.n_leaves * args.n * args.n
+    npts = f_host.size
     precs = ["split", "fp64"] if args.precision == "both" else [args.precision]
     res = {p: run_precision(args, p, tree, f_host) for p in precs}
     head = precs[0]                      # the mixed path when both run
@@ -208,8 +235,12 @@ def main():
         "dtype": "f64" if head == "fp64" else "i8-split+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "precision": head, "n_leaves": tree.n_leaves, "points": npts,
+                   "n_rhs": int(f_host.shape[0]) if f_host.ndim == 4 else 1,
+                   "trees": len(tree.trees) if isinstance(tree, Forest) else 1,
                    "nodes": args.n, "order": args.p, "levels": int(r["tree"].query("n_levels")),
-                   "tree_upload_ms": r["tree"].query("upload_ms"), "table_build_s": r["t_tables"]},
+                   "tree_upload_ms": r["tree"].query("upload_ms"), "table_build_s": r["t_tables"],
+                   "schedule": dict(zip(["heavy", "fp64_weight", "m2l_blocks"], r["tuning"])),
+                   "autotuned": bool(args.autotune)},
         "roofline": roofline_of(r, args, head),
         "phases": r["phases"],
     }
@@ -219,6 +250,7 @@ def main():
     if len(res) == 2:
         p = res["fp64"]
         out["plain_fp64"] = {"value": p["value"], "ms_per_step": p["ms_step"], "ms_per_step_profiled": p["ms_prof"],
+                             "schedule": dict(zip(["heavy", "fp64_weight", "m2l_blocks"], p["tuning"])),
                              "roofline": roofline_of(p, args, "fp64"), "phases": p["phases"]}
         out["mixed_vs_plain"] = r["value"] / p["value"]
         # the split result against the FP64 result over every node (the FP64 path
@@ -226,7 +258,9 @@ def main():
         s_, d_ = res["split"], res["fp64"]
         out["split_vs_fp64"] = {"E_V": rel_err(s_["V"], d_["V"]), "E_dV_dx1": rel_err(s_["G"][:, :, 0], d_["G"][:, :, 0]),
                                 "E_dV_dx2": rel_err(s_["G"][:, :, 1], d_["G"][:, :, 1])}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and (isinstance(tree, Forest) or f_host.ndim == 4):
+        log("cpu baseline: single-tree, single-RHS workloads only")
+    elif not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb, sel, vals = cpu_baseline(tree, f_host)
         check = {}

@@ -28,7 +28,7 @@ TABLES = dict(near=0, p2m=1, m2m=2, l2l=3, m2l_core=4, m2l_src_pow=5, m2l_tgt_po
 PHASES = ["p2m", "m2m", "m2l", "p2l", "l2l", "leaf"]
 SYMBOLS = ["bx_create", "bx_build_tables", "bx_tree_upload", "bx_volume_eval_grad", "bx_volume_eval",
            "bx_volume_grad", "bx_query", "bx_tree_list", "bx_table_copy", "bx_split_tolerance", "bx_profile",
-           "bx_interpolate",
+           "bx_interpolate", "bx_tree_tuning", "bx_tree_tuning_get", "bx_autotune",
            "bx_profile_read",
            "bx_tree_destroy", "bx_destroy", "bx_last_error"]
 
@@ -66,6 +66,9 @@ def lib():
         L.bx_table_copy.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
         L.bx_interpolate.argtypes = [vp, vp, vp, vp, i32, vp, i64, vp, vp, vp]
         L.bx_split_tolerance.argtypes = [vp, dp]
+        L.bx_tree_tuning.argtypes = [vp, vp, vp, vp]
+        L.bx_tree_tuning_get.argtypes = [vp, vp]
+        L.bx_autotune.argtypes = [vp, vp, vp, i32, vp, vp, i32, vp, vp]
         L.bx_profile.argtypes = [vp, i32]
         L.bx_profile_read.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(i32)]
         L.bx_tree_destroy.argtypes = [vp]
@@ -189,6 +192,17 @@ class Tree:
         _check(lib().bx_query(self.ctx._h, self._h, 40 + k, ctypes.byref(by)))
         return fl.value, by.value
 
+    def tuning(self):
+        """(heavy-tile threshold, FP64 slot weight, M2L blocks) of this tree's schedule."""
+        t = np.zeros(3)
+        _check(lib().bx_tree_tuning_get(self._h, t.ctypes.data))
+        return float(t[0]), float(t[1]), int(t[2])
+
+    def set_tuning(self, heavy=0.0, f64_weight=0.0, m2l_blocks=0, stream=None):
+        """Set scheduling parameters (0 keeps one); results do not change."""
+        t = np.array([heavy, f64_weight, m2l_blocks], np.float64)
+        _check(lib().bx_tree_tuning(self.ctx._h, self._h, t.ctypes.data, _stream_ptr(stream)))
+
     def lists(self, kind: int) -> np.ndarray:
         cnt = ctypes.c_int64()
         _check(lib().bx_tree_list(self._h, int(kind), None, 0, ctypes.byref(cnt)))
@@ -235,6 +249,27 @@ def volume_eval_grad(ctx: Context, tree: Tree, f, V=None, G=None, stream=None):
                                      ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(G.data_ptr()),
                                      _stream_ptr(stream)))
     return V, G
+
+
+def autotune(ctx: Context, tree: Tree, f, V=None, G=None, reps: int = 5, stream=None):
+    """Time candidate schedules of tree for f [n_rhs, N_L, n, n] and keep the fastest;
+    returns (V, G, (heavy, f64_weight, m2l_blocks, ms per evaluation))."""
+    import torch
+    if f.dim() == 3:
+        f = f.unsqueeze(0)
+    nrhs, n = f.shape[0], ctx.n
+    _dev_check(f, (nrhs, tree.n_leaves, n, n), "f")
+    V = torch.empty_like(f) if V is None else V
+    G = torch.empty((nrhs, tree.n_leaves, 2, n, n), dtype=f.dtype, device=f.device) if G is None else G
+    _dev_check(V, (nrhs, tree.n_leaves, n, n), "V")
+    _dev_check(G, (nrhs, tree.n_leaves, 2, n, n), "G")
+    if stream is None:
+        stream = torch.cuda.current_stream(f.device)
+    best = np.zeros(4)
+    _check(lib().bx_autotune(ctx._h, tree._h, ctypes.c_void_p(f.data_ptr()), int(nrhs),
+                             ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(G.data_ptr()), int(reps),
+                             best.ctypes.data, _stream_ptr(stream)))
+    return V, G, (float(best[0]), float(best[1]), int(best[2]), float(best[3]))
 
 
 def interpolate(ctx: Context, tree: Tree, xy, V=None, G=None, stream=None):

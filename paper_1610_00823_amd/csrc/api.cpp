@@ -55,6 +55,13 @@ struct bx_tree {
   int64_t n_slots = 0;
   int n_trees = 1;
   std::vector<int> box_tree;           // tree of each box (forests)
+  // host copies of the tilings, for rebuilding the work units (autotuning)
+  std::vector<int> h_tile_ptr, h_nslot_ptr, h_tile_nsl;
+  bool split = false;
+  std::vector<void *> unit_bufs;       // device work-unit arrays
+  double tune_heavy = 1.25;            // heavy-tile threshold, in balanced shares of a resident block
+  double tune_f64_weight = 4.0;        // split kernel: an FP64 slot's cost in int8 slice pairs
+  int tune_m2l_blocks = 1024;          // persistent M2L blocks
 };
 
 namespace bx {
@@ -249,8 +256,8 @@ void order_units(const std::vector<Unit> &units, std::vector<int> &unit_tile, st
 // wave << 16).  A unit costs about its slot count times its rows; tiles far
 // above the balanced share of one resident block are split by rows (one row
 // tile per wave), so that no single tile sets the kernel's duration.
-void leaf_units(const std::vector<int> &tile_ptr, int n, int blocks_per_cu, int n_cu, std::vector<int> &unit_tile,
-                std::vector<int> &unit_mt) {
+void leaf_units(const std::vector<int> &tile_ptr, int n, int blocks_per_cu, int n_cu, double heavy_factor,
+                std::vector<int> &unit_tile, std::vector<int> &unit_mt) {
   const int P = n * n, MTR = std::max(1, 3 * P / 16);
   const int TPW = n == 4 ? 1 : (n == 8 ? 3 : 4), G = (MTR + 4 * TPW - 1) / (4 * TPW);
   const int ntiles = (int)tile_ptr.size() - 1;
@@ -262,7 +269,7 @@ void leaf_units(const std::vector<int> &tile_ptr, int n, int blocks_per_cu, int 
   for (int tt = 0; tt < ntiles; ++tt) {
     const int ns = tile_ptr[tt + 1] - tile_ptr[tt];
     if (ns == 0) continue;
-    const bool heavy = TPW > 1 && cost_of(ns, TPW) > 1.25 * share;
+    const bool heavy = TPW > 1 && cost_of(ns, TPW) > heavy_factor * share;
     for (int gg = 0; gg < G; ++gg) {
       if (!heavy) units.push_back({tt, gg * 4 * TPW | TPW << 16, cost_of(ns, TPW)});
       else
@@ -273,6 +280,52 @@ void leaf_units(const std::vector<int> &tile_ptr, int n, int blocks_per_cu, int 
 }
 }  // namespace
 }  // namespace bx
+
+// Work units of the leaf kernels from the tree's tilings and tuning
+// parameters, uploaded (replacing earlier ones).
+static int upload_units(bx_ctx *ctx, bx_tree *t, hipStream_t s) {
+  std::vector<int> unit_tile, unit_mt, nunit_tile, nunit_mt;
+  leaf_units(t->h_tile_ptr, ctx->n, 2, ctx->n_cu, t->tune_heavy, unit_tile, unit_mt);
+  if (t->split) {   // int8 kernel: every tile (it writes V and G), 12 row tiles per block
+    const int MTR = 3 * ctx->n * ctx->n / 16, ntiles = (int)t->h_tile_nsl.size();
+    const std::vector<int> &tp = t->h_tile_ptr, &np = t->h_nslot_ptr, &nsl = t->h_tile_nsl;
+    // a unit's cost: its int8 slice pairs and its FP64 slots (weighted by a
+    // tuned number of pairs); tiles far above the balanced share of one
+    // resident block are split into thirds by rows (one row tile per wave)
+    auto cost_of = [&](int tt) {
+      const int sv = std::max(3, nsl[tt] & 255), sd = std::max(3, nsl[tt] >> 8);
+      const double pairs = (sv * (sv + 1) / 2.0 + 2.0 * sd * (sd + 1) / 2.0) / 3.0;
+      return 1.0 + (np[tt + 1] - np[tt]) * pairs + t->tune_f64_weight * (tp[tt + 1] - tp[tt]);
+    };
+    double total = 0;
+    for (int tt = 0; tt < ntiles; ++tt) total += cost_of(tt) * (MTR / 12);
+    const double share = total / std::max(1, ctx->n_cu);
+    std::vector<Unit> nu;
+    for (int tt = 0; tt < ntiles; ++tt) {
+      const double c = cost_of(tt);
+      const bool heavy = c > t->tune_heavy * share;
+      for (int mt0 = 0; mt0 < MTR; mt0 += 12) {
+        if (!heavy) nu.push_back({tt, mt0 | 3 << 16, c});
+        else
+          for (int j = 0; j < 3; ++j) nu.push_back({tt, (mt0 + 4 * j) | 1 << 16, c / 3 + 0.5});
+      }
+    }
+    order_units(nu, nunit_tile, nunit_mt);
+  }
+  for (void *p : t->unit_bufs) (void)hipFree(p);
+  t->unit_bufs.clear();
+  DevTree &g = t->dg;
+  int rc;
+  if ((rc = upload(t->unit_bufs, unit_tile, &g.unit_tile, s)) || (rc = upload(t->unit_bufs, unit_mt, &g.unit_mt, s)) ||
+      (rc = upload(t->unit_bufs, nunit_tile, &g.nunit_tile, s)) || (rc = upload(t->unit_bufs, nunit_mt, &g.nunit_mt, s)))
+    return rc;
+  g.n_units = (int)unit_tile.size();
+  g.n_nunits = (int)nunit_tile.size();
+  g.m2l_blocks = t->tune_m2l_blocks;
+  // the host vectors die here: the copies must have completed
+  hipError_t e = hipStreamSynchronize(s);
+  return e == hipSuccess ? BX_OK : hip_fail(e, "upload_units");
+}
 
 int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree **out, bx_stream_t stream) {
   if (!ctx || !trees || !out) return fail(BX_E_ARG, "bx_tree_upload: NULL argument");
@@ -402,36 +455,10 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
     tile_ptr[tt + 1] = (int)slot_type.size();
   }
   g.n_tiles = ntiles;
-  std::vector<int> unit_tile, unit_mt, nunit_tile, nunit_mt;
-  leaf_units(tile_ptr, ctx->n, 2, ctx->n_cu, unit_tile, unit_mt);
-  g.n_units = (int)unit_tile.size();
-  if (split) {   // int8 near kernel: every tile (it writes V and G), 12 row tiles per block
-    const int MTR = 3 * ctx->n * ctx->n / 16;
-    // a unit's cost: its int8 slice pairs and its FP64 slots (weighted 4 pairs:
-    // the weight that measured fastest; heavier weights split more tiles, and
-    // the split thirds repeat the B staging); tiles far above the balanced share
-    // of one resident block are split into thirds by rows (one row tile per wave)
-    auto cost_of = [&](int tt) {
-      const int sv = std::max(3, tile_nsl[tt] & 255), sd = std::max(3, tile_nsl[tt] >> 8);
-      const double pairs = (sv * (sv + 1) / 2.0 + 2.0 * sd * (sd + 1) / 2.0) / 3.0;
-      return 1.0 + (nslot_ptr[tt + 1] - nslot_ptr[tt]) * pairs + 4.0 * (tile_ptr[tt + 1] - tile_ptr[tt]);
-    };
-    double total = 0;
-    for (int tt = 0; tt < ntiles; ++tt) total += cost_of(tt) * (MTR / 12);
-    const double share = total / std::max(1, ctx->n_cu);
-    std::vector<Unit> nu;
-    for (int tt = 0; tt < ntiles; ++tt) {
-      const double c = cost_of(tt);
-      const bool heavy = c > 1.25 * share;
-      for (int mt0 = 0; mt0 < MTR; mt0 += 12) {
-        if (!heavy) nu.push_back({tt, mt0 | 3 << 16, c});
-        else
-          for (int j = 0; j < 3; ++j) nu.push_back({tt, (mt0 + 4 * j) | 1 << 16, c / 3 + 0.5});
-      }
-    }
-    order_units(nu, nunit_tile, nunit_mt);
-  }
-  g.n_nunits = (int)nunit_tile.size();
+  t->h_tile_ptr = tile_ptr;
+  t->h_nslot_ptr = nslot_ptr;
+  t->h_tile_nsl = tile_nsl;
+  t->split = split;
   g.split_sf = split_sf;
   t->split_sf = split_sf;
   // X-list tiles: target boxes with X entries, sorted by configuration set
@@ -533,12 +560,9 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       (rc = upload(t->dev, tile_tgt, &g.tile_tgt, s)) || (rc = upload(t->dev, tile_ptr, &g.tile_ptr, s)) ||
       (rc = upload(t->dev, slot_aoff, &g.slot_aoff, s)) || (rc = upload(t->dev, slot_type, &g.slot_type, s)) ||
       (rc = upload(t->dev, slot_op, &g.slot_op, s)) || (rc = upload(t->dev, tile_nsl, &g.tile_nsl, s)) ||
-      (rc = upload(t->dev, slot_src, &g.slot_src, s)) || (rc = upload(t->dev, unit_tile, &g.unit_tile, s)) ||
-      (rc = upload(t->dev, unit_mt, &g.unit_mt, s)) ||
+      (rc = upload(t->dev, slot_src, &g.slot_src, s)) || (rc = upload_units(ctx, t, s)) ||
       (split && ((rc = upload(t->dev, nslot_ptr, &g.nslot_ptr, s)) || (rc = upload(t->dev, nslot_cfg, &g.nslot_cfg, s)) ||
-                 (rc = upload(t->dev, nslot_src, &g.nslot_src, s)) ||
-                 (rc = upload(t->dev, nunit_tile, &g.nunit_tile, s)) ||
-                 (rc = upload(t->dev, nunit_mt, &g.nunit_mt, s))))) {
+                 (rc = upload(t->dev, nslot_src, &g.nslot_src, s))))) {
     bx_tree_destroy(t);
     return rc;
   }
@@ -729,6 +753,103 @@ int bx_interpolate(const bx_ctx *ctx, const bx_tree *tree, const double *V, cons
   return e == hipSuccess ? BX_OK : hip_fail(e, "bx_interpolate");
 }
 
+int bx_tree_tuning(bx_ctx *ctx, bx_tree *tree, const double tune[3], bx_stream_t stream) {
+  if (!ctx || !tree || !tune) return fail(BX_E_ARG, "bx_tree_tuning: NULL argument");
+  if (tree->ctx != ctx) return fail(BX_E_ARG, "bx_tree_tuning: tree belongs to another context");
+  if (tune[2] > 0 && (tune[2] != std::floor(tune[2]) || tune[2] > 65535))
+    return fail(BX_E_ARG, "bx_tree_tuning: M2L blocks must be an integer in [1, 65535]");
+  if (ctx->flags & BX_HOST_ONLY) return fail(BX_E_UNSUPPORTED, "bx_tree_tuning: host-only context");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipStreamSynchronize(s);   // no evaluation may still read the old work lists
+  if (e != hipSuccess) return hip_fail(e, "bx_tree_tuning");
+  if (tune[0] > 0) tree->tune_heavy = tune[0];
+  if (tune[1] > 0) tree->tune_f64_weight = tune[1];
+  if (tune[2] > 0) tree->tune_m2l_blocks = (int)tune[2];
+  drop_graphs(tree);
+  return upload_units(ctx, tree, s);
+}
+
+int bx_tree_tuning_get(const bx_tree *tree, double tune[3]) {
+  if (!tree || !tune) return fail(BX_E_ARG, "bx_tree_tuning_get: NULL argument");
+  tune[0] = tree->tune_heavy;
+  tune[1] = tree->tune_f64_weight;
+  tune[2] = tree->tune_m2l_blocks;
+  return BX_OK;
+}
+
+int bx_autotune(bx_ctx *ctx, bx_tree *tree, const double *f, int nrhs, double *V, double *G, int reps,
+                double best[4], bx_stream_t stream) {
+  if (!ctx || !tree || !V || !G) return fail(BX_E_ARG, "bx_autotune: NULL argument");
+  if (reps < 1) return fail(BX_E_ARG, "bx_autotune: reps < 1");
+  if (ctx->profiling) return fail(BX_E_ARG, "bx_autotune: profiling is enabled");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t he = hipEventCreate(&ev[0]);
+  if (he == hipSuccess) he = hipEventCreate(&ev[1]);
+  if (he != hipSuccess) {
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    return hip_fail(he, "bx_autotune events");
+  }
+  // median of 3 batches of `reps` evaluations (after one untimed evaluation,
+  // which also captures the graph), milliseconds per evaluation
+  auto time_it = [&](double *ms) -> int {
+    int rc = bx_volume_eval_grad(ctx, tree, f, nrhs, V, G, stream);
+    if (rc) return rc;
+    double t[3];
+    for (int k = 0; k < 3; ++k) {
+      hipError_t e = hipEventRecord(ev[0], s);
+      for (int r = 0; r < reps && !rc && e == hipSuccess; ++r) rc = bx_volume_eval_grad(ctx, tree, f, nrhs, V, G, stream);
+      if (rc) return rc;
+      if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      float x = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&x, ev[0], ev[1]);
+      if (e != hipSuccess) return hip_fail(e, "bx_autotune timing");
+      t[k] = x / reps;
+    }
+    std::sort(t, t + 3);
+    *ms = t[1];
+    return BX_OK;
+  };
+  double cur[3] = {tree->tune_heavy, tree->tune_f64_weight, (double)tree->tune_m2l_blocks};
+  double best_ms = 0;
+  int rc = bx_tree_tuning(ctx, tree, cur, stream);
+  if (!rc) rc = time_it(&best_ms);
+  static const double cand_m2l[] = {256, 512, 768, 1024, 1536, 2048};
+  static const double cand_heavy[] = {0.75, 1.0, 1.25, 1.5, 2.0, 1e30};
+  static const double cand_w[] = {1, 2, 4, 8, 16};
+  struct Axis { int k; const double *v; int n; };
+  const Axis axes[3] = {{2, cand_m2l, 6}, {0, cand_heavy, 6}, {1, cand_w, (ctx->flags & BX_SPLIT_INT8) ? 5 : 0}};
+  for (const Axis &a : axes) {
+    for (int i = 0; i < a.n && !rc; ++i) {
+      if (a.v[i] == cur[a.k]) continue;
+      double trial[3] = {cur[0], cur[1], cur[2]}, ms = 0;
+      trial[a.k] = a.v[i];
+      if ((rc = bx_tree_tuning(ctx, tree, trial, stream)) || (rc = time_it(&ms))) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        cur[a.k] = a.v[i];
+      }
+    }
+  }
+  // leave the best setting in place, with its result in V and G
+  if (!rc) rc = bx_tree_tuning(ctx, tree, cur, stream);
+  if (!rc) rc = bx_volume_eval_grad(ctx, tree, f, nrhs, V, G, stream);
+  if (!rc) {
+    he = hipStreamSynchronize(s);
+    if (he != hipSuccess) rc = hip_fail(he, "bx_autotune");
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (!rc && best) {
+    best[0] = cur[0];
+    best[1] = cur[1];
+    best[2] = cur[2];
+    best[3] = best_ms;
+  }
+  return rc;
+}
+
 int bx_split_tolerance(bx_ctx *ctx, double tol) {
   if (!ctx || !(tol > 0.0) || tol >= 1.0) return fail(BX_E_ARG, "bx_split_tolerance: need 0 < tol < 1");
   ctx->split_tol = tol;
@@ -917,6 +1038,7 @@ void bx_tree_destroy(bx_tree *tree) {
   if (tree->M) (void)hipFree(tree->M);
   if (tree->L) (void)hipFree(tree->L);
   free_split_buffers(tree);
+  for (void *p : tree->unit_bufs) (void)hipFree(p);
   delete tree;
 }
 

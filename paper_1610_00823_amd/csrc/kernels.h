@@ -42,7 +42,7 @@ struct DevTree {
   // the 6 x 6 grid of its target's parent)
   const int *v_ptr, *v_src, *v_cfg, *v_slot;
   // M2L sibling groups: the internal boxes and their 6 x 6 grids (box or -1)
-  int n_m2l_par;
+  int n_m2l_par, m2l_blocks;   // sibling groups, persistent M2L blocks
   const int *m2l_par;      // [n_m2l_par]
   const int *m2l_grid;     // [n_m2l_par][36]
   // W: per target leaf, CSR of (source box, config)

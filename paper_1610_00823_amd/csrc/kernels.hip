@@ -1035,7 +1035,8 @@ void launch_m2m(const DevTables &t, const DevTree &g, const int *boxes, int nbox
 }
 void launch_m2l(const DevTables &t, const DevTree &g, int nrhs, const double *M, double *L, hipStream_t s) {
   // blocks of contiguous parent ranges, plus one for the root
-  const int nb = g.n_m2l_par < M2L_BLOCKS ? (g.n_m2l_par > 0 ? g.n_m2l_par : 1) : M2L_BLOCKS;
+  const int mb = g.m2l_blocks > 0 ? g.m2l_blocks : M2L_BLOCKS;
+  const int nb = g.n_m2l_par < mb ? (g.n_m2l_par > 0 ? g.n_m2l_par : 1) : mb;
   const int per = g.n_m2l_par > 0 ? (g.n_m2l_par + nb - 1) / nb : 0;
   dim3 grid(nb + 1, nrhs);
   if (t.KP == 16) hipLaunchKernelGGL(m2l_mfma_kernel<16>, grid, dim3(256), 0, s, t, g, M, L, per);

@@ -274,8 +274,38 @@ def is_balanced(tree: Tree) -> bool:
     return len(lv) == tree.n_leaves
 
 
+def _forest_tree(args):
+    k, seed, n = args
+    r = np.random.default_rng([seed, k])
+    K, cap = int(r.integers(1, 41)), int(r.integers(6, 13))
+    src = random_gaussians(100000 * seed + k, K)
+    return gaussian_tree(src, n, 1e-10, cap), src
+
+
+def forest(count: int, seed: int = 0, n: int = 8, workers: int = 16):
+    """`count` trees of uneven depth: tree k draws its Gaussian count in [1, 40] and
+    its depth cap in [6, 12] from a generator seeded by (seed, k), and its sources
+    like the 20-Gaussian workload (seed 100000 seed + k); built in a process pool."""
+    import multiprocessing as mp
+    jobs = [(k, seed, n) for k in range(count)]
+    if workers > 1 and count > 1:
+        with mp.get_context("fork").Pool(min(workers, count)) as pool:
+            out = pool.map(_forest_tree, jobs)
+    else:
+        out = [_forest_tree(j) for j in jobs]
+    return [t for t, _ in out], [s for _, s in out]
+
+
 def workload(name: str, n: int = 8):
-    """The named synthetic workloads: returns (tree, source function)."""
+    """The named synthetic workloads: returns (tree, source function), or for a
+    forest (forest<count>_s<seed>) (list of trees, list of sources)."""
+    if name.startswith("forest"):
+        body = name[len("forest"):]
+        count, seed = (int(body.split("_s")[0]), int(body.split("_s")[1])) if "_s" in body else (int(body), 0)
+        return forest(count, seed, n)
+    if name.startswith("gauss20_cap"):                # the 20-Gaussian source, seed 0, another depth cap
+        src = random_gaussians(0, 20)
+        return gaussian_tree(src, n, 1e-10, int(name[len("gauss20_cap"):])), src
     if name.startswith("uniform") and name.endswith("_gauss"):   # uniform<depth>_gauss
         return uniform_tree(int(name[len("uniform"):-len("_gauss")])), centred_gaussian(0.1)
     if name.startswith("gauss20"):
