@@ -296,6 +296,20 @@ def forest(count: int, seed: int = 0, n: int = 8, workers: int = 16):
     return [t for t, _ in out], [s for _, s in out]
 
 
+def refine_net_init(seed: int) -> np.ndarray:
+    """Initial parameters of the refinement network (flat: W1[128][288], b1[128],
+    W2[128][128], b2[128], w3[128], b3[1]): He-uniform weights (bound
+    sqrt(6 / fan_in), fan_in 258 for the 258 live inputs of W1), zero biases,
+    drawn from default_rng(seed) in that order and rounded to FP32."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.uniform(-1, 1, (128, 288)) * np.sqrt(6.0 / 258.0)
+    W2 = rng.uniform(-1, 1, (128, 128)) * np.sqrt(6.0 / 128.0)
+    w3 = rng.uniform(-1, 1, 128) * np.sqrt(6.0 / 128.0)
+    z = np.zeros(128)
+    theta = np.concatenate([W1.ravel(), z, W2.ravel(), z, w3, np.zeros(1)])
+    return theta.astype(np.float32).astype(np.float64)
+
+
 def workload(name: str, n: int = 8):
     """The named synthetic workloads: returns (tree, source function), or for a
     forest (forest<count>_s<seed>) (list of trees, list of sources)."""
