@@ -263,6 +263,74 @@ void bx_tree_destroy(bx_tree *tree);
 void bx_destroy(bx_ctx *ctx);
 const char *bx_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Learned refinement (the adaptive refinement of section 3.1 proposed by a
+ * small network; the plain tail criterion still judges every leaf).
+ *
+ * A perceptron 288 -> 128 -> 128 -> 1 (ReLU) proposes whether a quadtree box
+ * is split.  Its inputs are features of the box (bx_mlp_features); its
+ * output is a logit, split proposed when positive.  Matrix products run on
+ * BF16 operands with FP32 sums; parameters, gradients and Adam moments are
+ * FP32.  Parameter vector (flat, BX_MLP_NPARAMS floats): W1[128][288],
+ * b1[128], W2[128][128], b2[128], w3[128], b3.
+ * ---------------------------------------------------------------------- */
+typedef struct bx_mlp bx_mlp;
+#define BX_MLP_IN 288
+#define BX_MLP_NPARAMS 53633
+
+/*
+ * Features of n_boxes boxes: samples_dev[n_boxes][16][16] (FP64, the source
+ * at the 16 x 16 first-kind Chebyshev points of each box, x index fastest)
+ * and level_dev[n_boxes] (int8) -> x_dev[n_boxes][288] BF16 (raw uint16):
+ * x[k] = s_k / max|s| (k < 256; 0 if all samples are 0), x[256] = level/16,
+ * x[257] = clip((log10 max|s| + 10) / 10, -1, 2) and x[258] =
+ * max(log10 max|s|, -320) / 320 (both -1 if all are 0), then zeros.  All device pointers, x_dev 16-byte aligned; stream-ordered.
+ * Errors: BX_E_ARG (NULL, n_boxes < 0, misaligned), BX_E_HIP.
+ */
+int bx_mlp_features(const double *samples_dev, const int8_t *level_dev, int64_t n_boxes, uint16_t *x_dev,
+                    bx_stream_t stream);
+
+/*
+ * Create a network on the current device with parameters params_host
+ * (BX_MLP_NPARAMS floats, copied; NULL: all zero) and zero Adam state.
+ * bx_mlp_set_params replaces the parameters and resets the Adam state.
+ * Both synchronize `stream`.  Errors: BX_E_ARG, BX_E_HIP, BX_E_OOM.
+ */
+int bx_mlp_create(bx_mlp **out, const float *params_host, bx_stream_t stream);
+int bx_mlp_set_params(bx_mlp *net, const float *params_host, bx_stream_t stream);
+
+/*
+ * Logits of n boxes: x_dev[n][288] BF16 (16-byte aligned) -> logit_dev[n]
+ * FP32.  Stream-ordered.  Errors: BX_E_ARG, BX_E_HIP.
+ */
+int bx_mlp_forward(const bx_mlp *net, const uint16_t *x_dev, int64_t n, float *logit_dev, bx_stream_t stream);
+
+/*
+ * Gradient of the mean binary cross-entropy of sigmoid(logit) against
+ * labels y_dev[n] (FP32, 0 or 1) over the n boxes x_dev, held in the
+ * network (read with bx_mlp_read); the mean loss likewise.  The products
+ * round h1 and the back-propagated dL/dz2 and dL/dz1 to BF16 as operands;
+ * sums over boxes use FP32 atomics, so their order (and the last bits)
+ * varies from call to call.  Stream-ordered.  Errors: BX_E_ARG, BX_E_HIP.
+ */
+int bx_mlp_grad(bx_mlp *net, const uint16_t *x_dev, const float *y_dev, int64_t n, bx_stream_t stream);
+
+/*
+ * One Adam step (Kingma and Ba) with the held gradient: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, w -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps),
+ * t counting the calls since the parameters were set.  Stream-ordered.
+ * Errors: BX_E_ARG (lr < 0, betas outside [0, 1), eps <= 0).
+ */
+int bx_mlp_adam(bx_mlp *net, float lr, float beta1, float beta2, float eps, bx_stream_t stream);
+
+/*
+ * Copy network state to the host (synchronizes `stream`): which 0 parameters,
+ * 1 gradient, 2 Adam m, 3 Adam v (BX_MLP_NPARAMS floats each), 4 the mean
+ * loss of the last bx_mlp_grad (1 float).  Errors: BX_E_ARG (cap too small).
+ */
+int bx_mlp_read(const bx_mlp *net, int which, float *out_host, int64_t cap, bx_stream_t stream);
+void bx_mlp_destroy(bx_mlp *net);
+
 #ifdef __cplusplus
 }
 #endif

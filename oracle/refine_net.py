@@ -11,7 +11,8 @@ FP64 from the definitions:
 * features x[288] of a box from its samples s on a 16 x 16 grid of
   first-kind Chebyshev points and its level l:
   A = max |s|, x[k] = s_k / A (k < 256; 0 when A = 0), x[256] = l / 16,
-  x[257] = clip((log10 A + 10) / 10, -1, 2) (-1 when A = 0), x[258:] = 0;
+  x[257] = clip((log10 A + 10) / 10, -1, 2) (-1 when A = 0),
+  x[258] = max(log10 A, -320) / 320 (-1 when A = 0), x[259:] = 0;
   every feature rounded to BF16 (round to nearest, ties to even);
 * the network 288 -> 128 -> 128 -> 1: z1 = x W1^T + b1, h1 = relu(z1),
   z2 = h1 W2^T + b2, h2 = relu(z2), logit = h2 . w3 + b3; the split is
@@ -75,7 +76,9 @@ def features(samples: np.ndarray, level: np.ndarray) -> np.ndarray:
     x[nz, :256] = s[nz] / A[nz, None]
     x[:, 256] = lv / 16.0
     with np.errstate(divide="ignore"):
-        x[:, 257] = np.where(nz, np.clip((np.log10(np.where(nz, A, 1.0)) + 10.0) / 10.0, -1.0, 2.0), -1.0)
+        lg = np.log10(np.where(nz, A, 1.0))
+        x[:, 257] = np.where(nz, np.clip((lg + 10.0) / 10.0, -1.0, 2.0), -1.0)
+        x[:, 258] = np.where(nz, np.maximum(lg, -320.0) / 320.0, -1.0)
     return bf16(x)
 
 

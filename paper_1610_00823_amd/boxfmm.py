@@ -29,7 +29,8 @@ PHASES = ["p2m", "m2m", "m2l", "p2l", "l2l", "leaf"]
 SYMBOLS = ["bx_create", "bx_build_tables", "bx_tree_upload", "bx_volume_eval_grad", "bx_volume_eval",
            "bx_volume_grad", "bx_query", "bx_tree_list", "bx_table_copy", "bx_split_tolerance", "bx_profile",
            "bx_interpolate", "bx_tree_tuning", "bx_tree_tuning_get", "bx_autotune",
-           "bx_profile_read",
+           "bx_profile_read", "bx_mlp_features", "bx_mlp_create", "bx_mlp_set_params", "bx_mlp_forward",
+           "bx_mlp_grad", "bx_mlp_adam", "bx_mlp_read", "bx_mlp_destroy",
            "bx_tree_destroy", "bx_destroy", "bx_last_error"]
 
 _lib = None
@@ -71,6 +72,14 @@ def lib():
         L.bx_autotune.argtypes = [vp, vp, vp, i32, vp, vp, i32, vp, vp]
         L.bx_profile.argtypes = [vp, i32]
         L.bx_profile_read.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(i32)]
+        L.bx_mlp_features.argtypes = [vp, vp, i64, vp, vp]
+        L.bx_mlp_create.argtypes = [ctypes.POINTER(vp), vp, vp]
+        L.bx_mlp_set_params.argtypes = [vp, vp, vp]
+        L.bx_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.bx_mlp_grad.argtypes = [vp, vp, vp, i64, vp]
+        L.bx_mlp_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
+        L.bx_mlp_read.argtypes = [vp, i32, vp, i64, vp]
+        L.bx_mlp_destroy.argtypes = [vp]
         L.bx_tree_destroy.argtypes = [vp]
         L.bx_destroy.argtypes = [vp]
         L.bx_last_error.restype = ctypes.c_char_p
@@ -79,6 +88,7 @@ def lib():
                 getattr(L, name).restype = i32
         L.bx_tree_destroy.restype = None
         L.bx_destroy.restype = None
+        L.bx_mlp_destroy.restype = None
         _lib = L
     return _lib
 
@@ -320,3 +330,90 @@ def volume_grad(ctx, tree, f, G=None, stream=None):
     _check(lib().bx_volume_grad(ctx._h, tree._h, ctypes.c_void_p(f.data_ptr()), int(nrhs),
                                 ctypes.c_void_p(G.data_ptr()), _stream_ptr(stream)))
     return G
+
+
+# ------------------------------------------------------------ refinement network
+MLP_IN, MLP_NPARAMS = 288, 53633
+
+
+def mlp_features(samples, level, stream=None):
+    """Features [B, 288] (torch.bfloat16, on the GPU) of boxes with samples
+    [B, 16, 16] (float64, GPU) on their 16 x 16 first-kind grids and levels [B] (int8, GPU)."""
+    import torch
+    B_ = samples.shape[0]
+    if not (samples.is_cuda and samples.dtype == torch.float64 and samples.is_contiguous()
+            and tuple(samples.shape[1:]) == (16, 16)):
+        raise ValueError("samples must be a contiguous float64 [B, 16, 16] GPU tensor")
+    if not (level.is_cuda and level.dtype == torch.int8 and level.shape == (B_,)):
+        raise ValueError("level must be an int8 [B] GPU tensor")
+    x = torch.empty((B_, MLP_IN), dtype=torch.bfloat16, device=samples.device)
+    stream = torch.cuda.current_stream(samples.device) if stream is None else stream
+    _check(lib().bx_mlp_features(ctypes.c_void_p(samples.data_ptr()), ctypes.c_void_p(level.data_ptr()), int(B_),
+                                 ctypes.c_void_p(x.data_ptr()), _stream_ptr(stream)))
+    return x
+
+
+class RefineNet:
+    """The refinement network on the GPU (BF16 products, FP32 parameters)."""
+
+    def __init__(self, params=None, stream=None):
+        self._h = ctypes.c_void_p()
+        p = None if params is None else np.ascontiguousarray(params, np.float32)
+        if p is not None and p.size != MLP_NPARAMS:
+            raise ValueError(f"expected {MLP_NPARAMS} parameters")
+        _check(lib().bx_mlp_create(ctypes.byref(self._h), None if p is None else p.ctypes.data, _stream_ptr(stream)))
+
+    def set_params(self, params, stream=None):
+        p = np.ascontiguousarray(params, np.float32)
+        if p.size != MLP_NPARAMS:
+            raise ValueError(f"expected {MLP_NPARAMS} parameters")
+        _check(lib().bx_mlp_set_params(self._h, p.ctypes.data, _stream_ptr(stream)))
+
+    def read(self, what: str = "params", stream=None) -> np.ndarray:
+        k = ["params", "grad", "adam_m", "adam_v", "loss"].index(what)
+        out = np.zeros(1 if k == 4 else MLP_NPARAMS, np.float32)
+        _check(lib().bx_mlp_read(self._h, k, out.ctypes.data, out.size, _stream_ptr(stream)))
+        return out
+
+    @staticmethod
+    def _x(x):
+        import torch
+        if not (x.is_cuda and x.dtype == torch.bfloat16 and x.is_contiguous() and x.dim() == 2
+                and x.shape[1] == MLP_IN and x.data_ptr() % 16 == 0):
+            raise ValueError("x must be a contiguous, 16-byte aligned bfloat16 [B, 288] GPU tensor")
+
+    def forward(self, x, stream=None):
+        """Logits [B] (float32, GPU) of features x [B, 288]."""
+        import torch
+        self._x(x)
+        out = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        stream = torch.cuda.current_stream(x.device) if stream is None else stream
+        _check(lib().bx_mlp_forward(self._h, ctypes.c_void_p(x.data_ptr()), int(x.shape[0]),
+                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def grad(self, x, y, stream=None):
+        """Gradient of the mean BCE against labels y [B] (float32, GPU), held in the network."""
+        import torch
+        self._x(x)
+        if not (y.is_cuda and y.dtype == torch.float32 and y.is_contiguous() and y.shape == (x.shape[0],)):
+            raise ValueError("y must be a contiguous float32 [B] GPU tensor")
+        stream = torch.cuda.current_stream(x.device) if stream is None else stream
+        _check(lib().bx_mlp_grad(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                 int(x.shape[0]), _stream_ptr(stream)))
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        import torch
+        stream = torch.cuda.current_stream() if stream is None else stream
+        _check(lib().bx_mlp_adam(self._h, lr, beta1, beta2, eps, _stream_ptr(stream)))
+
+    def close(self):
+        if self._h:
+            lib().bx_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

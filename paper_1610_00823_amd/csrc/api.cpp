@@ -11,6 +11,7 @@
 
 #include "bx_internal.h"
 #include "kernels.h"
+#include "mlp.h"
 
 struct bx_ctx {
   int n = 0, p = 0, device = 0;
@@ -62,6 +63,12 @@ struct bx_tree {
   double tune_heavy = 1.25;            // heavy-tile threshold, in balanced shares of a resident block
   double tune_f64_weight = 4.0;        // split kernel: an FP64 slot's cost in int8 slice pairs
   int tune_m2l_blocks = 1024;          // persistent M2L blocks
+};
+
+struct bx_mlp {
+  bx::MlpDev d{};
+  int step = 0;          // Adam steps since the parameters were set
+  void *block = nullptr; // one allocation for every buffer
 };
 
 namespace bx {
@@ -1048,6 +1055,112 @@ void bx_destroy(bx_ctx *ctx) {
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   for (void *p : ctx->dev) (void)hipFree(p);
   delete ctx;
+}
+
+int bx_mlp_features(const double *samples_dev, const int8_t *level_dev, int64_t n_boxes, uint16_t *x_dev,
+                    bx_stream_t stream) {
+  if (n_boxes < 0 || (n_boxes > 0 && (!samples_dev || !level_dev || !x_dev)))
+    return fail(BX_E_ARG, "bx_mlp_features: NULL pointer or n_boxes < 0");
+  if (((uintptr_t)x_dev & 15) || ((uintptr_t)samples_dev & 7)) return fail(BX_E_ARG, "bx_mlp_features: misaligned");
+  launch_mlp_features(samples_dev, level_dev, (long long)n_boxes, x_dev, (hipStream_t)stream);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BX_OK : hip_fail(e, "bx_mlp_features");
+}
+
+int bx_mlp_set_params(bx_mlp *net, const float *params_host, bx_stream_t stream) {
+  if (!net) return fail(BX_E_ARG, "bx_mlp_set_params: NULL network");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = (size_t)MLP_NPARAM * sizeof(float);
+  hipError_t e = params_host ? hipMemcpyAsync(net->d.theta, params_host, bytes, hipMemcpyHostToDevice, s)
+                             : hipMemsetAsync(net->d.theta, 0, bytes, s);
+  if (e == hipSuccess) e = hipMemsetAsync(net->d.m, 0, bytes, s);
+  if (e == hipSuccess) e = hipMemsetAsync(net->d.v, 0, bytes, s);
+  if (e == hipSuccess) e = hipMemsetAsync(net->d.grad, 0, bytes, s);
+  if (e == hipSuccess) e = hipMemsetAsync(net->d.loss, 0, sizeof(float), s);
+  if (e == hipSuccess) {
+    launch_mlp_refresh(net->d, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // params_host may die after the call
+  if (e != hipSuccess) return hip_fail(e, "bx_mlp_set_params");
+  net->step = 0;
+  return BX_OK;
+}
+
+int bx_mlp_create(bx_mlp **out, const float *params_host, bx_stream_t stream) {
+  if (!out) return fail(BX_E_ARG, "bx_mlp_create: NULL output");
+  *out = nullptr;
+  bx_mlp *net = new bx_mlp;
+  const size_t nf = ((size_t)MLP_NPARAM + 63) / 64 * 64;            // floats per FP32 array, 256-byte multiple
+  const size_t bytes = 4 * nf * sizeof(float) + 256 +                  // theta, grad, m, v; loss
+                       (size_t)(MLP_HID * MLP_IN + 2 * MLP_HID * MLP_HID) * sizeof(uint16_t);
+  hipError_t e = hipMalloc(&net->block, bytes);
+  if (e != hipSuccess) {
+    delete net;
+    return e == hipErrorOutOfMemory ? fail(BX_E_OOM, "bx_mlp_create") : hip_fail(e, "bx_mlp_create");
+  }
+  float *f = (float *)net->block;
+  net->d.theta = f;
+  net->d.grad = f + nf;
+  net->d.m = f + 2 * nf;
+  net->d.v = f + 3 * nf;
+  net->d.loss = f + 4 * nf;
+  uint16_t *h = (uint16_t *)(f + 4 * nf + 64);
+  net->d.w1b = h;
+  net->d.w2b = h + MLP_HID * MLP_IN;
+  net->d.w2tb = net->d.w2b + MLP_HID * MLP_HID;
+  int rc = bx_mlp_set_params(net, params_host, stream);
+  if (rc) {
+    bx_mlp_destroy(net);
+    return rc;
+  }
+  *out = net;
+  return BX_OK;
+}
+
+int bx_mlp_forward(const bx_mlp *net, const uint16_t *x_dev, int64_t n, float *logit_dev, bx_stream_t stream) {
+  if (!net || n < 0 || (n > 0 && (!x_dev || !logit_dev))) return fail(BX_E_ARG, "bx_mlp_forward: bad argument");
+  if ((uintptr_t)x_dev & 15) return fail(BX_E_ARG, "bx_mlp_forward: x_dev must be 16-byte aligned");
+  launch_mlp_forward(net->d, x_dev, (long long)n, logit_dev, (hipStream_t)stream);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BX_OK : hip_fail(e, "bx_mlp_forward");
+}
+
+int bx_mlp_grad(bx_mlp *net, const uint16_t *x_dev, const float *y_dev, int64_t n, bx_stream_t stream) {
+  if (!net || n < 0 || (n > 0 && (!x_dev || !y_dev))) return fail(BX_E_ARG, "bx_mlp_grad: bad argument");
+  if ((uintptr_t)x_dev & 15) return fail(BX_E_ARG, "bx_mlp_grad: x_dev must be 16-byte aligned");
+  launch_mlp_grad(net->d, x_dev, y_dev, (long long)n, (hipStream_t)stream);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BX_OK : hip_fail(e, "bx_mlp_grad");
+}
+
+int bx_mlp_adam(bx_mlp *net, float lr, float beta1, float beta2, float eps, bx_stream_t stream) {
+  if (!net || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(BX_E_ARG, "bx_mlp_adam: need lr >= 0, 0 <= betas < 1, eps > 0");
+  const int t = net->step + 1;
+  const double c1 = 1.0 / (1.0 - std::pow((double)beta1, t)), c2 = 1.0 / (1.0 - std::pow((double)beta2, t));
+  launch_mlp_adam(net->d, lr, beta1, beta2, eps, (float)c1, (float)c2, (hipStream_t)stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "bx_mlp_adam");
+  net->step = t;
+  return BX_OK;
+}
+
+int bx_mlp_read(const bx_mlp *net, int which, float *out_host, int64_t cap, bx_stream_t stream) {
+  if (!net || !out_host || which < 0 || which > 4) return fail(BX_E_ARG, "bx_mlp_read: bad argument");
+  const float *src[5] = {net->d.theta, net->d.grad, net->d.m, net->d.v, net->d.loss};
+  const int64_t count = which == 4 ? 1 : MLP_NPARAM;
+  if (cap < count) return fail(BX_E_ARG, "bx_mlp_read: cap too small");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(out_host, src[which], count * sizeof(float), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? BX_OK : hip_fail(e, "bx_mlp_read");
+}
+
+void bx_mlp_destroy(bx_mlp *net) {
+  if (!net) return;
+  if (net->block) (void)hipFree(net->block);
+  delete net;
 }
 
 }  // extern "C"

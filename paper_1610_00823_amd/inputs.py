@@ -203,54 +203,90 @@ def balance(level, ix, iy):
     return lv, xs, ys
 
 
+def box_grid(level, bx, by, m: int, cx=0.0, cy=0.0, width=1.0):
+    """Coordinates X, Y [B, m, m] (x index fastest) of the m x m first-kind
+    Chebyshev points of boxes (level, bx, by)."""
+    xi = cheb1_nodes(m)
+    lv = np.asarray(level, np.int64)
+    h = width * np.ldexp(1.0, -lv)
+    x0 = cx - 0.5 * width + np.asarray(bx, np.int64) * h
+    y0 = cy - 0.5 * width + np.asarray(by, np.int64) * h
+    X = (x0 + 0.5 * h)[:, None, None] + 0.5 * h[:, None, None] * xi[None, None, :]
+    Y = (y0 + 0.5 * h)[:, None, None] + 0.5 * h[:, None, None] * xi[None, :, None]
+    B = len(lv)
+    return np.broadcast_to(X, (B, m, m)), np.broadcast_to(Y, (B, m, m))
+
+
+def split_decision(fun: Callable, level, bx, by, n: int, tol: float, max_level: int, min_level: int = 0,
+                   cx=0.0, cy=0.0, width=1.0, seed_points=None, seed_widths=None, weight: str = "none"):
+    """The plain criterion's decision for boxes (level, bx, by): split when the
+    tail of the n x n interpolant exceeds tol (weighted by h^2 or h with
+    weight='area' / 'side'), below min_level, or (seed rule) when the box holds
+    a seed point and is wider than 4 of its widths; never at max_level.
+    Returns (split [B] bool, f evaluations used)."""
+    lv = np.asarray(level, np.int64)
+    if len(lv) == 0:
+        return np.zeros(0, bool), 0
+    X, Y = box_grid(lv, bx, by, n, cx, cy, width)
+    vals = np.asarray(fun(X, Y), np.float64)
+    h = width * np.ldexp(1.0, -lv)
+    tail = _cheb_tail(vals, n)
+    if weight == "area":
+        tail = tail * h * h
+    elif weight == "side":
+        tail = tail * h
+    split = (tail > tol) | (lv < min_level)
+    if seed_points is not None:
+        x0 = cx - 0.5 * width + np.asarray(bx, np.int64) * h
+        y0 = cy - 0.5 * width + np.asarray(by, np.int64) * h
+        for (px, py), sg in zip(seed_points, seed_widths):
+            inside = (px >= x0) & (px < x0 + h) & (py >= y0) & (py < y0 + h)
+            split |= inside & (h > 4.0 * sg)
+    split &= lv < max_level
+    return split, vals.size
+
+
 def adaptive_tree(fun: Callable, n: int, tol: float = 1e-10, max_level: int = 14,
                   min_level: int = 0, cx=0.0, cy=0.0, width=1.0,
                   seed_points: Optional[np.ndarray] = None, seed_widths: Optional[np.ndarray] = None,
-                  weight: str = "none") -> Tree:
+                  weight: str = "none", record: Optional[list] = None, roots=None) -> Tree:
     """Top-down refinement with the tail criterion, then 2:1 balance.
 
     weight='none' compares the tail itself with tol; weight='area' multiplies it
     by the box area (h^2) and 'side' by the side length, the weighted variants of
-    section 6.1.
+    section 6.1.  With `record` (a list) every visited box is appended as
+    arrays (level, bx, by, split) per level.  `roots` (level, bx, by arrays)
+    starts the refinement from those boxes instead of the root; their
+    refinement is returned unbalanced (meta 'leaves').
     """
-    xi = cheb1_nodes(n)
-    todo = [(0, 0, 0)]
-    leaves = []
+    if roots is None:
+        todo = (np.zeros(1, np.int64), np.zeros(1, np.int64), np.zeros(1, np.int64))
+    else:
+        todo = tuple(np.asarray(a, np.int64) for a in roots)
+    leaves = [[], [], []]
     n_evals = 0
-    while todo:
-        lv = np.array([b[0] for b in todo], np.int64)
-        bx = np.array([b[1] for b in todo], np.int64)
-        by = np.array([b[2] for b in todo], np.int64)
-        h = width * np.ldexp(1.0, -lv)
-        x0 = cx - 0.5 * width + bx * h
-        y0 = cy - 0.5 * width + by * h
-        X = (x0 + 0.5 * h)[:, None, None] + 0.5 * h[:, None, None] * xi[None, None, :]
-        Y = (y0 + 0.5 * h)[:, None, None] + 0.5 * h[:, None, None] * xi[None, :, None]
-        vals = fun(np.broadcast_to(X, (len(todo), n, n)), np.broadcast_to(Y, (len(todo), n, n)))
-        n_evals += vals.size
-        tail = _cheb_tail(np.asarray(vals, np.float64), n)
-        if weight == "area":
-            tail = tail * h * h
-        elif weight == "side":
-            tail = tail * h
-        split = (tail > tol) | (lv < min_level)
-        if seed_points is not None:
-            for (px, py), s in zip(seed_points, seed_widths):
-                inside = (px >= x0) & (px < x0 + h) & (py >= y0) & (py < y0 + h)
-                split |= inside & (h > 4.0 * s)
-        split &= lv < max_level
-        nxt = []
-        for i, b in enumerate(todo):
-            if split[i]:
-                l, x, y = b
-                nxt += [(l + 1, 2 * x + cxx, 2 * y + cyy) for cyy in (0, 1) for cxx in (0, 1)]
-            else:
-                leaves.append(b)
-        todo = nxt
-    lv, xs, ys = balance([b[0] for b in leaves], [b[1] for b in leaves], [b[2] for b in leaves])
-    return Tree(lv, xs, ys, cx, cy, width,
-                {"kind": "adaptive", "tol": tol, "max_level": max_level, "n": n,
-                 "leaves_before_balance": len(leaves), "f_evals": n_evals})
+    while len(todo[0]):
+        lv, bx, by = todo
+        split, ne = split_decision(fun, lv, bx, by, n, tol, max_level, min_level, cx, cy, width, seed_points,
+                                   seed_widths, weight)
+        n_evals += ne
+        if record is not None:
+            record.append((lv, bx, by, split))
+        keep = ~split
+        for k, a in enumerate((lv, bx, by)):
+            leaves[k].append(a[keep])
+        sl, sx, sy = lv[split], bx[split], by[split]
+        cxx = np.array([0, 1, 0, 1])
+        cyy = np.array([0, 0, 1, 1])
+        todo = (np.repeat(sl + 1, 4), (2 * sx[:, None] + cxx).ravel(), (2 * sy[:, None] + cyy).ravel())
+    lv, xs, ys = (np.concatenate(a) for a in leaves)
+    meta = {"kind": "adaptive", "tol": tol, "max_level": max_level, "n": n, "leaves_before_balance": len(lv),
+            "f_evals": n_evals}
+    if roots is not None:
+        meta["leaves"] = (lv, xs, ys)
+        return Tree(lv.astype(np.int8), xs.astype(np.int32), ys.astype(np.int32), cx, cy, width, meta)
+    lv, xs, ys = balance(lv, xs, ys)
+    return Tree(lv, xs, ys, cx, cy, width, meta)
 
 
 def gaussian_tree(src: GaussianSum, n: int, tol=1e-10, max_level=14) -> Tree:

@@ -42,11 +42,15 @@ def test_features_invariances():
     A = np.abs(s.reshape(5, -1)).max(1)
     assert np.allclose(x2[:, 257], R.bf16((np.log10(A * 2.0 ** -20) + 10) / 10), rtol=0, atol=0)
     assert np.all(np.abs(x[:, :256]).max(1) == 1.0)
-    assert np.array_equal(x[:, 256], lv / 16.0) and np.all(x[:, 258:] == 0)
+    assert np.array_equal(x[:, 256], lv / 16.0) and np.all(x[:, 259:] == 0)
     z = R.features(np.zeros((1, 16, 16)), [4])
-    assert np.all(z[0, :256] == 0) and z[0, 257] == -1.0
+    assert np.all(z[0, :256] == 0) and z[0, 257] == -1.0 and z[0, 258] == -1.0
     big = R.features(np.full((1, 16, 16), 1e30), [0])
-    assert big[0, 257] == 2.0
+    assert big[0, 257] == 2.0 and big[0, 258] == R.bf16(30 / 320)
+    # a faint trace (all samples near 1e-200) saturates the first amplitude
+    # feature but not the second
+    faint = R.features(np.full((1, 16, 16), 1e-200), [0])
+    assert faint[0, 257] == -1.0 and faint[0, 258] == R.bf16(-200 / 320)
 
 
 @pytest.mark.parametrize("emulate", [False, True])
