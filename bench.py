@@ -164,6 +164,49 @@ class Forest:
         self.n_leaves = sum(t.n_leaves for t in trees)
 
 
+def learned_forest(count, n, cap=9):
+    """Train the refinement network on the plain criterion's decisions (with the
+    seed rule) for seeded sums of 1-40 and of 20 Gaussians and the kink source,
+    then build trees for `count` fresh sums of 1-8 Gaussians (seeds 10000 + i)
+    with the network proposing and the plain tail criterion checking."""
+    from paper_1610_00823_amd import inputs as I
+    from paper_1610_00823_amd import refine as RF
+    t0 = time.perf_counter()
+    jobs = (RF.source_jobs(range(300, 348), kinds=("gaussK",), n=n, cap=cap)
+            + RF.source_jobs(range(400, 412), kinds=("gauss20",), n=n, cap=cap)
+            + RF.source_jobs([0], kinds=("kink",), n=n, cap=cap))
+    s, lv, y = RF.labelled_boxes(jobs, workers=16)   # host processes, before the GPU is touched
+    t_labels = time.perf_counter() - t0
+    import torch
+    ref = RF.LearnedRefiner(seed=0)
+    x = ref.features(s, lv)
+    del s
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = ref.train(x, y, epochs=8, batch=1024, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    live = lv < cap
+    acc = float((ref.predict(x)[live] == (y[live] > 0.5)).mean())
+    del x
+    funs = [I.random_gaussians(10000 + i, int(np.random.default_rng([10000 + i, 7]).integers(1, 9)))
+            for i in range(count)]
+    trees, st = ref.build(funs, n=n, cap=cap)
+    plain, plain_ev = RF.plain_trees(funs[:32], n=n, cap=cap)
+    e_l = [RF.resolution_error(t, f, n, points=f.c) for t, f in zip(trees[:32], funs[:32])]
+    e_p = [RF.resolution_error(t, f, n, points=f.c) for t, f in zip(plain, funs[:32])]
+    missed = [i for i in range(len(plain)) if e_p[i] > 1e-3]
+    info = {"training_boxes": int(len(y)), "labels_s": round(t_labels, 1), "train_s": round(t_train, 2),
+            "final_loss": round(losses[-1], 4), "accuracy_below_cap": round(acc, 4), "cap": cap,
+            "net_boxes": st.net_boxes, "proposed_leaves": st.proposed_leaves, "fallback_leaves": st.failed_leaves,
+            "f_evals": st.f_evals, "build_s": {k: round(v, 2) for k, v in st.seconds.items()},
+            "first32": {"plain_missed_bump": len(missed), "learned_resolved": sum(e_l[i] < 1e-3 for i in missed),
+                        "leaves_learned": sum(t.n_leaves for t in trees[:32]),
+                        "leaves_plain": sum(t.n_leaves for t in plain), "f_evals_plain": plain_ev}}
+    log(f"learned refinement: {info}")
+    return trees, funs, info
+
+
 def rel_err(a, b):
     return float((a - b).abs().max() / b.abs().max())
 
@@ -206,7 +249,11 @@ def main():
     from paper_1610_00823_amd import inputs as I
 
     t0 = time.perf_counter()
-    tree, src = I.workload(args.workload, args.n)
+    learned = None
+    if args.workload.startswith("learned"):          # trees proposed by the trained network
+        tree, src, learned = learned_forest(int(args.workload[7:] or 256), args.n)
+    else:
+        tree, src = I.workload(args.workload, args.n)
     if isinstance(tree, list):                       # a forest: one upload, one evaluation
         f_host = np.concatenate([I.sample(t, s_, args.n) for t, s_ in zip(tree, src)])
         tree = Forest(tree)
@@ -244,6 +291,8 @@ def main():
         "roofline": roofline_of(r, args, head),
         "phases": r["phases"],
     }
+    if learned is not None:
+        out["config"]["learned_refinement"] = learned
     if "split" in res:
         out["config"]["split_tolerance"] = 1e-11
         out["config"]["split_mean_slice_products"] = res["split"]["split_products"]
