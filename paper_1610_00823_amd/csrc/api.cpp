@@ -503,7 +503,7 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
   // one level below P's 3 x 3 neighbourhood (children of P's colleagues), from
   // which the V lists of P's four children are drawn; each V entry records the
   // grid slot of its source.
-  std::vector<int> m2l_par, m2l_grid, v_slot(vs.size(), -1);
+  std::vector<int> m2l_par, m2l_grid, v_slot(vs.size(), -1), m2l_ent, m2l_info;
   {
     std::vector<std::unordered_map<uint64_t, int>> at_tree(t->n_trees);   // per tree: key -> box
     for (int b = 0; b < H.n_boxes; ++b) at_tree[t->box_tree[b]][box_key(H.lvl[b], H.bx[b], H.by[b])] = b;
@@ -532,7 +532,18 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
           }
           v_slot[e] = gy * 6 + gx;
         }
+        // packed entries of this child: slot | offset class << 8, padded with -1
+        if (vp[tb + 1] - vp[tb] > M2L_VMAX) {
+          bx_tree_destroy(t);
+          return fail(BX_E_INVALID_TREE, "bx_tree_upload: V list longer than 32");
+        }
+        for (int j = 0; j < M2L_VMAX; ++j) {
+          const int e = vp[tb] + j;
+          m2l_ent.push_back(e < vp[tb + 1] ? v_slot[e] | vc[e] << 8 : -1);
+        }
       }
+      m2l_info.push_back(H.child0[P]);
+      m2l_info.push_back(l + 1);
     }
     g.n_m2l_par = (int)m2l_par.size();
   }
@@ -564,6 +575,7 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       (rc = upload(t->dev, xslot_cfg, &g.xslot_cfg, s)) || (rc = upload(t->dev, xslot_src, &g.xslot_src, s)) ||
       (rc = upload(t->dev, ib, &t->int_boxes, s)) || (rc = upload(t->dev, m2l_par, &g.m2l_par, s)) ||
       (rc = upload(t->dev, m2l_grid, &g.m2l_grid, s)) || (rc = upload(t->dev, v_slot, &g.v_slot, s)) ||
+      (rc = upload(t->dev, m2l_ent, &g.m2l_ent, s)) || (rc = upload(t->dev, m2l_info, &g.m2l_info, s)) ||
       (rc = upload(t->dev, tile_tgt, &g.tile_tgt, s)) || (rc = upload(t->dev, tile_ptr, &g.tile_ptr, s)) ||
       (rc = upload(t->dev, slot_aoff, &g.slot_aoff, s)) || (rc = upload(t->dev, slot_type, &g.slot_type, s)) ||
       (rc = upload(t->dev, slot_op, &g.slot_op, s)) || (rc = upload(t->dev, tile_nsl, &g.tile_nsl, s)) ||

@@ -26,6 +26,8 @@ struct DevTables {
 };
 
 // Device copy of a tree's hierarchy and lists (CSR by target, sorted).
+constexpr int M2L_VMAX = 32;   // longest V list (27) rounded up to 4 groups of 8
+
 struct DevTree {
   int n_leaves, n_boxes, n_levels;
   double width, cx, cy;      // root width and centre (of the first tree of a forest)
@@ -45,6 +47,8 @@ struct DevTree {
   int n_m2l_par, m2l_blocks;   // sibling groups, persistent M2L blocks
   const int *m2l_par;      // [n_m2l_par]
   const int *m2l_grid;     // [n_m2l_par][36]
+  const int *m2l_ent;      // [n_m2l_par][4 children][M2L_VMAX]: grid slot | offset class << 8, or -1
+  const int *m2l_info;     // [n_m2l_par][2]: first child box, child level
   // W: per target leaf, CSR of (source box, config)
   const int *w_ptr, *w_src, *w_cfg;
   // X: per target box, CSR of (source leaf, config)

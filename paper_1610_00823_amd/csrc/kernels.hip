@@ -222,9 +222,11 @@ __global__ void __launch_bounds__(256) p2m_mfma_kernel(DevTables t, DevTree g, c
 // expansion; the last block writes the roots' zero expansions.
 constexpr int M2L_BLOCKS = 1024;
 
+
 template <int KPT>
-__global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, const double *__restrict__ M,
-                                                       double *__restrict__ L, int per_block) {
+__global__ void __launch_bounds__(256, KPT <= 32 ? 2 : 1) m2l_mfma_kernel(DevTables t, DevTree g,
+                                                                               const double *__restrict__ M,
+                                                                               double *__restrict__ L, int per_block) {
   constexpr int MT = KPT / 16, KS = KPT / 4;
   constexpr int PWS = KPT + 1;                 // padded rows: 8 offsets / sources per column group, distinct banks
   constexpr int GPT = (36 * KPT + 255) / 256;  // grid coefficients per thread
@@ -254,10 +256,19 @@ __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, c
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) hA[m][ks] = t.H[(size_t)(m * 16 + col) * KPT + kq * KS + ks];
-  // this thread's share of a parent's grid: coefficient i = threadIdx.x + 256 j
+  // this thread's share of a parent's grid: coefficient i = threadIdx.x + 256 j;
+  // this lane's V entries (iteration it: entry 8 it + col/2 of its wave's
+  // child) and the parent's first child and level, all requested one parent
+  // ahead so that no load waits inside the source loop
   double2 gm[GPT];
+  int en[4];
+  int2 inf;
   auto grid_load = [&](int pp) {
     const int *grid = g.m2l_grid + (size_t)pp * 36;
+    const int *ep = g.m2l_ent + ((size_t)pp * 4 + wave) * M2L_VMAX + (col >> 1);
+#pragma unroll
+    for (int it = 0; it < 4; ++it) en[it] = ep[8 * it];
+    inf = ((const int2 *)g.m2l_info)[pp];
 #pragma unroll
     for (int j = 0; j < GPT; ++j) {
       const int i = threadIdx.x + 256 * j, sl = i < 36 * KPT ? i / KPT : 0;
@@ -274,23 +285,23 @@ __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, c
       const int i = threadIdx.x + 256 * j;
       if (i < 36 * KPT) sM[i / KPT * PWS + i % KPT] = gm[j];
     }
+    int ent[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) ent[it] = en[it];
+    const int box = inf.x + wave;
+    const double logh = log(box_h(g.width, inf.y));
     __syncthreads();
     if (pp + 1 < p1) grid_load(pp + 1);        // in flight during this parent's products
-    const int box = g.child0[g.m2l_par[pp]] + wave;
     double acc[MT][4];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[m][r] = 0.0;
     double a0 = 0.0;
-    const double logh = log(box_h(g.width, g.lvl[box]));
-    const int e0 = g.v_ptr[box], e1 = g.v_ptr[box + 1];
-    for (int e = e0; e < e1; e += 8) {
-      // this lane's source e + col/2 (a valid entry is read even past the end)
-      const int pe = e + (col >> 1);
-      const bool ok = pe < e1;
-      const int pc = ok ? pe : e1 - 1;
-      const int s_c = g.v_slot[pc], o_c = g.v_cfg[pc];
+    // one group of 8 V entries (dead lanes and dead groups add zeros)
+    auto group = [&](int it) {
+      const bool ok = ent[it] >= 0;
+      const int s_c = ok ? ent[it] & 255 : 0, o_c = ok ? ent[it] >> 8 : 0;
       double bv[KS];
       const double2 *ap = &sM[s_c * PWS + kq * KS];
       const double2 *wp = &spw[0][o_c * PWS + kq * KS];
@@ -319,6 +330,16 @@ __global__ void __launch_bounds__(256) m2l_mfma_kernel(DevTables t, DevTree g, c
           const double v = part ? zr * q.y + zi * q.x : zr * q.x - zi * q.y;
           acc[m][r] += ok ? v : 0.0;
         }
+    };
+    // entries are packed from the front: group it is live when its first entry
+    // is.  Groups run in pairs with no branch between them, so that one's
+    // products overlap the other's operand building (a dead second group adds
+    // zeros); the launch bound keeps two waves per SIMD.
+#pragma unroll
+    for (int it = 0; it < 4; it += 2) {
+      if (__builtin_amdgcn_readfirstlane(ent[it]) < 0) break;
+      group(it);
+      group(it + 1);
     }
     // sum over the 8 sources of each column group (lanes with equal kq and part)
 #pragma unroll
