@@ -94,33 +94,65 @@ __global__ void __launch_bounds__(256) m2m_mfma_kernel(DevTables t, DevTree g, c
 // c = blockIdx.z: A = L2L_c (2KP x 2KP), B = the parent's local expansion; wave
 // w computes row tile w (of MT), so each wave's chain is short.  The result is
 // added to the child's local expansion.
-template <int KPT>
+template <int KPT, bool WIDE>
 __global__ void __launch_bounds__(256) l2l_mfma_kernel(DevTables t, DevTree g, const int *__restrict__ boxes,
                                                        int nbox, double *__restrict__ L) {
-  constexpr int R = 2 * KPT, MT = R / 16, KS = R / 4;
+  // Each wave computes row tiles of one child position c for 16 parents: all
+  // of them (c = wave) or, for levels with few boxes (WIDE: four times the
+  // blocks), tiles wave, wave + 4, ... (c = blockIdx.z).  The parent's
+  // expansion, the operator fragments and the child's current expansion are
+  // all requested before the products, so a level costs one memory round trip.
+  constexpr int R = 2 * KPT, MT = R / 16, KS = R / 4, NT = WIDE ? (MT + 3) / 4 : MT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
-  const int i = blockIdx.x * 16 + col, rhs = blockIdx.y, c = blockIdx.z;
+  const int c = WIDE ? blockIdx.z : wave;
+  const int i = blockIdx.x * 16 + col, rhs = blockIdx.y;
   const bool ok = i < nbox;
   const int box = ok ? boxes[i] : 0;
   double *Lr = L + (size_t)rhs * g.n_boxes * R;
   const double *bp = Lr + (size_t)box * R + kq * KS;
+  double *Lc = Lr + (size_t)(ok ? g.child0[box] + c : 0) * R;
   const double *A = t.l2l_frag + (size_t)c * MT * KS * 64;
-  double bv[KS];
+  int tm[NT];                                     // row tile of slot m (MT when there is none)
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) bv[ks] = bp[ks];      // the parent's expansion, one round trip
-  for (int m = wave; m < MT; m += 4) {
-    double av[KS];
+  for (int m = 0; m < NT; ++m) tm[m] = WIDE ? (wave + 4 * m < MT ? wave + 4 * m : MT) : m;
+  dbl4 acc[NT];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) av[ks] = A[((size_t)m * KS + ks) * 64 + lane];
-    dbl4 acc = dbl4{0, 0, 0, 0};
+  for (int m = 0; m < NT; ++m) acc[m] = dbl4{0, 0, 0, 0};
+  double old[NT][4];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) acc = mfma4(av[ks], ok ? bv[ks] : 0.0, acc);
-    if (ok) {
-      double *Lc = Lr + (size_t)(g.child0[box] + c) * R;
+  for (int m = 0; m < NT; ++m)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Lc[m * 16 + 4 * r + kq] += acc[r];
+    for (int r = 0; r < 4; ++r) old[m][r] = Lc[(tm[m] < MT ? tm[m] : 0) * 16 + 4 * r + kq];
+  if constexpr (KPT <= 32) {
+    double bv[KS], av[NT][KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) bv[ks] = bp[ks];
+#pragma unroll
+    for (int m = 0; m < NT; ++m)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) av[m][ks] = A[((size_t)(tm[m] < MT ? tm[m] : 0) * KS + ks) * 64 + lane];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int m = 0; m < NT; ++m) acc[m] = mfma4(av[m][ks], ok ? bv[ks] : 0.0, acc[m]);
+  } else {
+    for (int ks = 0; ks < KS; ks += 4) {
+      double bv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = bp[ks + j];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int m = 0; m < NT; ++m)
+          acc[m] = mfma4(A[((size_t)(tm[m] < MT ? tm[m] : 0) * KS + ks + j) * 64 + lane], ok ? bv[j] : 0.0, acc[m]);
     }
   }
+  if (ok)
+#pragma unroll
+    for (int m = 0; m < NT; ++m)
+      if (tm[m] < MT)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Lc[tm[m] * 16 + 4 * r + kq] = old[m][r] + acc[m][r];
 }
 
 // X list: b~ += h^2 P2L_c f_s, b~_0 += h^2 log h (4 W . f_s), over 16-box tiles
@@ -1074,10 +1106,19 @@ void launch_p2l(const DevTables &t, const DevTree &g, const double *f, int nrhs,
 void launch_l2l(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *L,
                 hipStream_t s) {
   if (nbox <= 0) return;
-  dim3 grid((nbox + 15) / 16, nrhs, 4);
-  if (t.KP == 16) hipLaunchKernelGGL(l2l_mfma_kernel<16>, grid, dim3(256), 0, s, t, g, boxes, nbox, L);
-  else if (t.KP == 32) hipLaunchKernelGGL(l2l_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, boxes, nbox, L);
-  else hipLaunchKernelGGL(l2l_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, boxes, nbox, L);
+  // levels with fewer than two blocks per CU of 16 parents spread the four
+  // child positions over blocks as well
+  const bool wide = (long long)(nbox + 15) / 16 * nrhs < 512;
+  dim3 grid((nbox + 15) / 16, nrhs, wide ? 4 : 1);
+  if (wide) {
+    if (t.KP == 16) hipLaunchKernelGGL((l2l_mfma_kernel<16, true>), grid, dim3(256), 0, s, t, g, boxes, nbox, L);
+    else if (t.KP == 32) hipLaunchKernelGGL((l2l_mfma_kernel<32, true>), grid, dim3(256), 0, s, t, g, boxes, nbox, L);
+    else hipLaunchKernelGGL((l2l_mfma_kernel<48, true>), grid, dim3(256), 0, s, t, g, boxes, nbox, L);
+  } else {
+    if (t.KP == 16) hipLaunchKernelGGL((l2l_mfma_kernel<16, false>), grid, dim3(256), 0, s, t, g, boxes, nbox, L);
+    else if (t.KP == 32) hipLaunchKernelGGL((l2l_mfma_kernel<32, false>), grid, dim3(256), 0, s, t, g, boxes, nbox, L);
+    else hipLaunchKernelGGL((l2l_mfma_kernel<48, false>), grid, dim3(256), 0, s, t, g, boxes, nbox, L);
+  }
 }
 void launch_leaf(const DevTables &t, const DevTree &g, const double *f, int nrhs, const double *M,
                  const double *L, double *V, double *G, bool accumulate, hipStream_t s) {
