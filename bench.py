@@ -107,7 +107,7 @@ def run_precision(args, precision, tree, f_host):
         t0 = time.perf_counter()
         _, _, tuning = B.autotune(ctx, tr, f, V, G, reps=3, stream=stream)
         log(f"{precision}: autotune {time.perf_counter() - t0:.1f} s: heavy {tuning[0]}, fp64 weight "
-            f"{tuning[1]}, m2l blocks {tuning[2]}, {tuning[3]:.4f} ms")
+            f"{tuning[1]}, m2l blocks {tuning[2]}, two-level threshold {tuning[3]}, {tuning[4]:.4f} ms")
     for _ in range(args.warmup):
         B.volume_eval_grad(ctx, tr, f, V, G, stream)
     torch.cuda.synchronize()
@@ -286,7 +286,7 @@ def main():
                    "trees": len(tree.trees) if isinstance(tree, Forest) else 1,
                    "nodes": args.n, "order": args.p, "levels": int(r["tree"].query("n_levels")),
                    "tree_upload_ms": r["tree"].query("upload_ms"), "table_build_s": r["t_tables"],
-                   "schedule": dict(zip(["heavy", "fp64_weight", "m2l_blocks"], r["tuning"])),
+                   "schedule": dict(zip(["heavy", "fp64_weight", "m2l_blocks", "two_level_max"], r["tuning"])),
                    "autotuned": bool(args.autotune)},
         "roofline": roofline_of(r, args, head),
         "phases": r["phases"],
@@ -299,7 +299,7 @@ def main():
     if len(res) == 2:
         p = res["fp64"]
         out["plain_fp64"] = {"value": p["value"], "ms_per_step": p["ms_step"], "ms_per_step_profiled": p["ms_prof"],
-                             "schedule": dict(zip(["heavy", "fp64_weight", "m2l_blocks"], p["tuning"])),
+                             "schedule": dict(zip(["heavy", "fp64_weight", "m2l_blocks", "two_level_max"], p["tuning"])),
                              "roofline": roofline_of(p, args, "fp64"), "phases": p["phases"]}
         out["mixed_vs_plain"] = r["value"] / p["value"]
         # the split result against the FP64 result over every node (the FP64 path

@@ -207,28 +207,33 @@ int bx_split_tolerance(bx_ctx *ctx, double tol);
  *           of the balanced per-block share is split by rows (default 1.25);
  *   tune[1] split contexts: cost of one FP64 slot of the near kernel, in int8
  *           slice pairs, for that balance (default 4);
- *   tune[2] persistent M2L blocks (default 1024).
- * bx_tree_tuning sets them (a value <= 0 keeps the current one), rebuilds the
- * work lists on the device (allocates; synchronizes `stream`) and drops
- * captured evaluation graphs.  bx_tree_tuning_get copies the current ones.
- * Errors: BX_E_ARG (NULL, tune[2] not an integer in [1, 65535]), BX_E_HIP, BX_E_OOM.
+ *   tune[2] persistent M2L blocks (default 1024);
+ *   tune[3] M2M and L2L run two levels per launch where the middle level has
+ *           at most this many internal boxes (default 512; 0: never).
+ * bx_tree_tuning sets them (tune[0..2] <= 0 or tune[3] = -1 keeps the current
+ * value), rebuilds the work lists on the device (allocates; synchronizes
+ * `stream`) and drops captured evaluation graphs.  bx_tree_tuning_get copies
+ * the current ones.
+ * Errors: BX_E_ARG (NULL, tune[2] not an integer in [1, 65535], tune[3] not an
+ * integer >= -1), BX_E_HIP, BX_E_OOM.
  */
-int bx_tree_tuning(bx_ctx *ctx, bx_tree *tree, const double tune[3], bx_stream_t stream);
-int bx_tree_tuning_get(const bx_tree *tree, double tune[3]);
+int bx_tree_tuning(bx_ctx *ctx, bx_tree *tree, const double tune[4], bx_stream_t stream);
+int bx_tree_tuning_get(const bx_tree *tree, double tune[4]);
 
 /*
  * Autotune a tree's scheduling parameters for one evaluation shape: runs
  * bx_volume_eval_grad(f_dev, n_rhs, V_dev, G_dev) for candidate settings, one
- * parameter at a time (M2L blocks, heavy threshold, FP64 slot weight), each
+ * parameter at a time (M2L blocks, heavy threshold, FP64 slot weight,
+ * two-level threshold), each
  * timed with device events as the median of 3 batches of `reps` evaluations,
  * and keeps the fastest.  V_dev and G_dev hold that evaluation's result on
- * return.  best (may be NULL) receives the chosen tune[0..2] and, in best[3],
+ * return.  best (may be NULL) receives the chosen tune[0..3] and, in best[4],
  * the median milliseconds per evaluation with them.  Synchronizes `stream`;
  * not for use while other work on the tree is in flight.
  * Errors: as bx_volume_eval_grad and bx_tree_tuning; BX_E_ARG if reps < 1.
  */
 int bx_autotune(bx_ctx *ctx, bx_tree *tree, const double *f_dev, int n_rhs, double *V_dev, double *G_dev,
-                int reps, double best[4], bx_stream_t stream);
+                int reps, double best[5], bx_stream_t stream);
 
 /*
  * The piecewise polynomial v~ of section 3.1 (the interpolant, on each leaf, of

@@ -203,14 +203,14 @@ class Tree:
         return fl.value, by.value
 
     def tuning(self):
-        """(heavy-tile threshold, FP64 slot weight, M2L blocks) of this tree's schedule."""
-        t = np.zeros(3)
+        """(heavy-tile threshold, FP64 slot weight, M2L blocks, two-level threshold) of this tree's schedule."""
+        t = np.zeros(4)
         _check(lib().bx_tree_tuning_get(self._h, t.ctypes.data))
-        return float(t[0]), float(t[1]), int(t[2])
+        return float(t[0]), float(t[1]), int(t[2]), int(t[3])
 
-    def set_tuning(self, heavy=0.0, f64_weight=0.0, m2l_blocks=0, stream=None):
-        """Set scheduling parameters (0 keeps one); results do not change."""
-        t = np.array([heavy, f64_weight, m2l_blocks], np.float64)
+    def set_tuning(self, heavy=0.0, f64_weight=0.0, m2l_blocks=0, fuse=-1, stream=None):
+        """Set scheduling parameters (0, or -1 for fuse, keeps one); results do not change."""
+        t = np.array([heavy, f64_weight, m2l_blocks, fuse], np.float64)
         _check(lib().bx_tree_tuning(self.ctx._h, self._h, t.ctypes.data, _stream_ptr(stream)))
 
     def lists(self, kind: int) -> np.ndarray:
@@ -263,7 +263,7 @@ def volume_eval_grad(ctx: Context, tree: Tree, f, V=None, G=None, stream=None):
 
 def autotune(ctx: Context, tree: Tree, f, V=None, G=None, reps: int = 5, stream=None):
     """Time candidate schedules of tree for f [n_rhs, N_L, n, n] and keep the fastest;
-    returns (V, G, (heavy, f64_weight, m2l_blocks, ms per evaluation))."""
+    returns (V, G, (heavy, f64_weight, m2l_blocks, fuse, ms per evaluation))."""
     import torch
     if f.dim() == 3:
         f = f.unsqueeze(0)
@@ -275,11 +275,11 @@ def autotune(ctx: Context, tree: Tree, f, V=None, G=None, reps: int = 5, stream=
     _dev_check(G, (nrhs, tree.n_leaves, 2, n, n), "G")
     if stream is None:
         stream = torch.cuda.current_stream(f.device)
-    best = np.zeros(4)
+    best = np.zeros(5)
     _check(lib().bx_autotune(ctx._h, tree._h, ctypes.c_void_p(f.data_ptr()), int(nrhs),
                              ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(G.data_ptr()), int(reps),
                              best.ctypes.data, _stream_ptr(stream)))
-    return V, G, (float(best[0]), float(best[1]), int(best[2]), float(best[3]))
+    return V, G, (float(best[0]), float(best[1]), int(best[2]), int(best[3]), float(best[4]))
 
 
 def interpolate(ctx: Context, tree: Tree, xy, V=None, G=None, stream=None):

@@ -63,6 +63,7 @@ struct bx_tree {
   double tune_heavy = 1.25;            // heavy-tile threshold, in balanced shares of a resident block
   double tune_f64_weight = 4.0;        // split kernel: an FP64 slot's cost in int8 slice pairs
   int tune_m2l_blocks = 1024;          // persistent M2L blocks
+  int tune_fuse = 512;                // two-level M2M / L2L launches when the middle level has at most this many internal boxes
 };
 
 struct bx_mlp {
@@ -660,15 +661,31 @@ static int enqueue_eval(bx_ctx *ctx, bx_tree *t, const double *f, int nrhs, doub
   if ((rc = mark(BX_PH_P2M, true))) return rc;
   launch_p2m(d, g, f, nrhs, t->M, s);
   if ((rc = mark(BX_PH_P2M, false)) || (rc = mark(BX_PH_M2M, true))) return rc;
-  for (int l = H.n_levels - 2; l >= 0; --l)
-    launch_m2m(d, g, t->int_boxes + t->int_start[l], t->int_start[l + 1] - t->int_start[l], nrhs, t->M, s);
+  // levels whose internal boxes are few run two to a launch (latency-bound otherwise)
+  auto n_int = [&](int l) { return t->int_start[l + 1] - t->int_start[l]; };
+  for (int l = H.n_levels - 2; l >= 0;) {
+    if (l >= 1 && n_int(l) <= t->tune_fuse) {
+      launch_m2m2(d, g, t->int_boxes + t->int_start[l - 1], n_int(l - 1), nrhs, t->M, s);
+      l -= 2;
+    } else {
+      launch_m2m(d, g, t->int_boxes + t->int_start[l], n_int(l), nrhs, t->M, s);
+      l -= 1;
+    }
+  }
   if ((rc = mark(BX_PH_M2M, false)) || (rc = mark(BX_PH_M2L, true))) return rc;
   launch_m2l(d, g, nrhs, t->M, t->L, s);
   if ((rc = mark(BX_PH_M2L, false)) || (rc = mark(BX_PH_P2L, true))) return rc;
   launch_p2l(d, g, f, nrhs, t->L, s);
   if ((rc = mark(BX_PH_P2L, false)) || (rc = mark(BX_PH_L2L, true))) return rc;
-  for (int l = 0; l + 1 < H.n_levels; ++l)
-    launch_l2l(d, g, t->int_boxes + t->int_start[l], t->int_start[l + 1] - t->int_start[l], nrhs, t->L, s);
+  for (int l = 0; l + 1 < H.n_levels;) {
+    if (l + 2 < H.n_levels && n_int(l + 1) <= t->tune_fuse) {
+      launch_l2l2(d, g, t->int_boxes + t->int_start[l], n_int(l), nrhs, t->L, s);
+      l += 2;
+    } else {
+      launch_l2l(d, g, t->int_boxes + t->int_start[l], n_int(l), nrhs, t->L, s);
+      l += 1;
+    }
+  }
   if ((rc = mark(BX_PH_L2L, false)) || (rc = mark(BX_PH_LEAF, true))) return rc;
   if (ctx->flags & BX_SPLIT_INT8) {
     launch_split_prep(d, g, f, nrhs, t->fpart, t->fscale, t->fsl, t->lmass, s);
@@ -772,11 +789,13 @@ int bx_interpolate(const bx_ctx *ctx, const bx_tree *tree, const double *V, cons
   return e == hipSuccess ? BX_OK : hip_fail(e, "bx_interpolate");
 }
 
-int bx_tree_tuning(bx_ctx *ctx, bx_tree *tree, const double tune[3], bx_stream_t stream) {
+int bx_tree_tuning(bx_ctx *ctx, bx_tree *tree, const double tune[4], bx_stream_t stream) {
   if (!ctx || !tree || !tune) return fail(BX_E_ARG, "bx_tree_tuning: NULL argument");
   if (tree->ctx != ctx) return fail(BX_E_ARG, "bx_tree_tuning: tree belongs to another context");
   if (tune[2] > 0 && (tune[2] != std::floor(tune[2]) || tune[2] > 65535))
     return fail(BX_E_ARG, "bx_tree_tuning: M2L blocks must be an integer in [1, 65535]");
+  if (tune[3] != std::floor(tune[3]) || tune[3] < -1 || tune[3] > 1e9)
+    return fail(BX_E_ARG, "bx_tree_tuning: the two-level threshold must be an integer >= -1");
   if (ctx->flags & BX_HOST_ONLY) return fail(BX_E_UNSUPPORTED, "bx_tree_tuning: host-only context");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipStreamSynchronize(s);   // no evaluation may still read the old work lists
@@ -784,20 +803,22 @@ int bx_tree_tuning(bx_ctx *ctx, bx_tree *tree, const double tune[3], bx_stream_t
   if (tune[0] > 0) tree->tune_heavy = tune[0];
   if (tune[1] > 0) tree->tune_f64_weight = tune[1];
   if (tune[2] > 0) tree->tune_m2l_blocks = (int)tune[2];
+  if (tune[3] >= 0) tree->tune_fuse = (int)tune[3];   // -1 keeps it; 0 turns two-level launches off
   drop_graphs(tree);
   return upload_units(ctx, tree, s);
 }
 
-int bx_tree_tuning_get(const bx_tree *tree, double tune[3]) {
+int bx_tree_tuning_get(const bx_tree *tree, double tune[4]) {
   if (!tree || !tune) return fail(BX_E_ARG, "bx_tree_tuning_get: NULL argument");
   tune[0] = tree->tune_heavy;
   tune[1] = tree->tune_f64_weight;
   tune[2] = tree->tune_m2l_blocks;
+  tune[3] = tree->tune_fuse;
   return BX_OK;
 }
 
 int bx_autotune(bx_ctx *ctx, bx_tree *tree, const double *f, int nrhs, double *V, double *G, int reps,
-                double best[4], bx_stream_t stream) {
+                double best[5], bx_stream_t stream) {
   if (!ctx || !tree || !V || !G) return fail(BX_E_ARG, "bx_autotune: NULL argument");
   if (reps < 1) return fail(BX_E_ARG, "bx_autotune: reps < 1");
   if (ctx->profiling) return fail(BX_E_ARG, "bx_autotune: profiling is enabled");
@@ -830,19 +851,21 @@ int bx_autotune(bx_ctx *ctx, bx_tree *tree, const double *f, int nrhs, double *V
     *ms = t[1];
     return BX_OK;
   };
-  double cur[3] = {tree->tune_heavy, tree->tune_f64_weight, (double)tree->tune_m2l_blocks};
+  double cur[4] = {tree->tune_heavy, tree->tune_f64_weight, (double)tree->tune_m2l_blocks, (double)tree->tune_fuse};
   double best_ms = 0;
   int rc = bx_tree_tuning(ctx, tree, cur, stream);
   if (!rc) rc = time_it(&best_ms);
   static const double cand_m2l[] = {256, 512, 768, 1024, 1536, 2048};
   static const double cand_heavy[] = {0.75, 1.0, 1.25, 1.5, 2.0, 1e30};
   static const double cand_w[] = {1, 2, 4, 8, 16};
+  static const double cand_fuse[] = {0, 512, 2048, 8192};
   struct Axis { int k; const double *v; int n; };
-  const Axis axes[3] = {{2, cand_m2l, 6}, {0, cand_heavy, 6}, {1, cand_w, (ctx->flags & BX_SPLIT_INT8) ? 5 : 0}};
+  const Axis axes[4] = {{2, cand_m2l, 6}, {0, cand_heavy, 6}, {1, cand_w, (ctx->flags & BX_SPLIT_INT8) ? 5 : 0},
+                        {3, cand_fuse, 4}};
   for (const Axis &a : axes) {
     for (int i = 0; i < a.n && !rc; ++i) {
       if (a.v[i] == cur[a.k]) continue;
-      double trial[3] = {cur[0], cur[1], cur[2]}, ms = 0;
+      double trial[4] = {cur[0], cur[1], cur[2], cur[3]}, ms = 0;
       trial[a.k] = a.v[i];
       if ((rc = bx_tree_tuning(ctx, tree, trial, stream)) || (rc = time_it(&ms))) break;
       if (ms < best_ms) {
@@ -864,7 +887,8 @@ int bx_autotune(bx_ctx *ctx, bx_tree *tree, const double *f, int nrhs, double *V
     best[0] = cur[0];
     best[1] = cur[1];
     best[2] = cur[2];
-    best[3] = best_ms;
+    best[3] = cur[3];
+    best[4] = best_ms;
   }
   return rc;
 }

@@ -90,6 +90,11 @@ void launch_p2m(const DevTables &t, const DevTree &g, const double *f, int nrhs,
 // Upward pass step for the internal boxes `boxes` of one level.
 void launch_m2m(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *M,
                 hipStream_t s);
+// two levels per launch: boxes = internal boxes of the upper level
+void launch_m2m2(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *M,
+                 hipStream_t s);
+void launch_l2l2(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *L,
+                 hipStream_t s);
 void launch_m2l(const DevTables &t, const DevTree &g, int nrhs, const double *M, double *L, hipStream_t s);
 void launch_p2l(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *L, hipStream_t s);
 // Downward pass step from the internal boxes `boxes` of one level to their children.

@@ -94,6 +94,146 @@ __global__ void __launch_bounds__(256) m2m_mfma_kernel(DevTables t, DevTree g, c
 // c = blockIdx.z: A = L2L_c (2KP x 2KP), B = the parent's local expansion; wave
 // w computes row tile w (of MT), so each wave's chain is short.  The result is
 // added to the child's local expansion.
+// Two levels in one launch, for levels too small to fill the chip (one
+// launch each would be latency-bound).  A block takes 4 boxes G of the top
+// level and their 16 children Q (column j = 4 g + q).
+//   M2M: M(Q) = sum_c M2M_c M(child c of Q) for internal Q (stage 1, wave =
+//   c, all 16 columns), then M(G) = sum_q M2M_q M(Q_q) (stage 2, wave = q,
+//   columns 0..3); leaf children keep their P2M multipoles.
+//   L2L: L(Q) += L2L_q L(G) (stage 1, wave = q, columns 0..3), then
+//   L(child c of Q) += L2L_c L(Q) for internal Q (stage 2, wave = c).
+// Both stages stage their 16 (or 4) columns through LDS.
+template <int KPT>
+__device__ inline void gemm_cols(const double *A, const double *bcol, bool ok, int lane, int kq, dbl4 *acc) {
+  // acc[m] = A (MT row tiles of the 2 KP x 2 KP operator) times this lane's
+  // column; up to KP = 32 every operand is requested before the first product
+  constexpr int R = 2 * KPT, MT = R / 16, KS = R / 4;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) acc[m] = dbl4{0, 0, 0, 0};
+  if constexpr (KPT <= 32) {
+    double bv[KS], av[MT][KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) bv[ks] = ok ? bcol[kq * KS + ks] : 0.0;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) av[m][ks] = A[((size_t)m * KS + ks) * 64 + lane];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int m = 0; m < MT; ++m) acc[m] = mfma4(av[m][ks], bv[ks], acc[m]);
+  } else {
+    for (int ks = 0; ks < KS; ks += 4) {
+      double bv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = ok ? bcol[kq * KS + ks + j] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m] = mfma4(A[((size_t)m * KS + ks + j) * 64 + lane], bv[j], acc[m]);
+    }
+  }
+}
+
+template <int KPT>
+__global__ void __launch_bounds__(256) m2m2_mfma_kernel(DevTables t, DevTree g, const int *__restrict__ boxes,
+                                                        int nbox, double *__restrict__ M) {
+  constexpr int R = 2 * KPT, MT = R / 16, RP = R + 1;
+  __shared__ double part[4][16][RP];
+  __shared__ double sQ[16][RP];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
+  const int rhs = blockIdx.y;
+  double *Mr = M + (size_t)rhs * g.n_boxes * R;
+  // stage 1: column col = child Q (4 g + q) of top box g of this block
+  const int gi = blockIdx.x * 4 + (col >> 2);
+  const bool gok = gi < nbox;
+  const int Q = gok ? g.child0[boxes[gi]] + (col & 3) : 0;
+  const bool qint = gok && g.child0[Q] >= 0;
+  dbl4 acc[MT];
+  gemm_cols<KPT>(t.m2m_frag + (size_t)w * MT * (R / 4) * 64, Mr + (size_t)(qint ? g.child0[Q] + w : 0) * R, qint,
+                 lane, kq, acc);
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[w][col][m * 16 + 4 * r + kq] = acc[m][r];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 16 * R; e += 256) {
+    const int cc = e / R, row = e % R, gg = blockIdx.x * 4 + (cc >> 2);
+    if (gg >= nbox) continue;
+    const int q = g.child0[boxes[gg]] + (cc & 3);
+    if (g.child0[q] >= 0) {
+      const double v = ((part[0][cc][row] + part[1][cc][row]) + part[2][cc][row]) + part[3][cc][row];
+      sQ[cc][row] = v;
+      Mr[(size_t)q * R + row] = v;
+    } else {
+      sQ[cc][row] = Mr[(size_t)q * R + row];     // a leaf: its P2M multipole
+    }
+  }
+  __syncthreads();
+  // stage 2: column col < 4 = top box col, wave = child position q
+  const int g2 = blockIdx.x * 4 + col;
+  const bool ok2 = col < 4 && g2 < nbox;
+  gemm_cols<KPT>(t.m2m_frag + (size_t)w * MT * (R / 4) * 64, &sQ[ok2 ? col * 4 + w : 0][0], ok2, lane, kq, acc);
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[w][col][m * 16 + 4 * r + kq] = acc[m][r];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 4 * R; e += 256) {
+    const int cc = e / R, row = e % R, gg = blockIdx.x * 4 + cc;
+    if (gg < nbox)
+      Mr[(size_t)boxes[gg] * R + row] = ((part[0][cc][row] + part[1][cc][row]) + part[2][cc][row]) + part[3][cc][row];
+  }
+}
+
+template <int KPT>
+__global__ void __launch_bounds__(256) l2l2_mfma_kernel(DevTables t, DevTree g, const int *__restrict__ boxes,
+                                                        int nbox, double *__restrict__ L) {
+  constexpr int R = 2 * KPT, MT = R / 16, RP = R + 1;
+  __shared__ double sQ[16][RP];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
+  const int rhs = blockIdx.y;
+  double *Lr = L + (size_t)rhs * g.n_boxes * R;
+  // stage 1: column col < 4 = top box G, wave = child position q: L(Q) += L2L_q L(G)
+  const int g1 = blockIdx.x * 4 + col;
+  const bool ok1 = col < 4 && g1 < nbox;
+  const int G = ok1 ? boxes[g1] : 0;
+  const int Q1 = ok1 ? g.child0[G] + w : 0;
+  double old[MT][4];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) old[m][r] = Lr[(size_t)Q1 * R + m * 16 + 4 * r + kq];
+  dbl4 acc[MT];
+  gemm_cols<KPT>(t.l2l_frag + (size_t)w * MT * (R / 4) * 64, Lr + (size_t)G * R, ok1, lane, kq, acc);
+  if (ok1)
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double v = old[m][r] + acc[m][r];
+        sQ[col * 4 + w][m * 16 + 4 * r + kq] = v;
+        Lr[(size_t)Q1 * R + m * 16 + 4 * r + kq] = v;
+      }
+  __syncthreads();
+  // stage 2: column col = child Q (4 g + q), wave = grandchild position c
+  const int gi = blockIdx.x * 4 + (col >> 2);
+  const bool gok = gi < nbox;
+  const int Q = gok ? g.child0[boxes[gi]] + (col & 3) : 0;
+  const bool qint = gok && g.child0[Q] >= 0;
+  const int C = qint ? g.child0[Q] + w : 0;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) old[m][r] = Lr[(size_t)C * R + m * 16 + 4 * r + kq];
+  gemm_cols<KPT>(t.l2l_frag + (size_t)w * MT * (R / 4) * 64, &sQ[col][0], qint, lane, kq, acc);
+  if (qint)
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Lr[(size_t)C * R + m * 16 + 4 * r + kq] = old[m][r] + acc[m][r];
+}
+
 template <int KPT, bool WIDE>
 __global__ void __launch_bounds__(256) l2l_mfma_kernel(DevTables t, DevTree g, const int *__restrict__ boxes,
                                                        int nbox, double *__restrict__ L) {
@@ -1085,6 +1225,22 @@ void launch_m2m(const DevTables &t, const DevTree &g, const int *boxes, int nbox
   if (t.KP == 16) hipLaunchKernelGGL(m2m_mfma_kernel<16>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
   else if (t.KP == 32) hipLaunchKernelGGL(m2m_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
   else hipLaunchKernelGGL(m2m_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
+}
+void launch_m2m2(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *M,
+                 hipStream_t s) {
+  if (nbox <= 0) return;
+  dim3 grid((nbox + 3) / 4, nrhs);
+  if (t.KP == 16) hipLaunchKernelGGL(m2m2_mfma_kernel<16>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
+  else if (t.KP == 32) hipLaunchKernelGGL(m2m2_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
+  else hipLaunchKernelGGL(m2m2_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
+}
+void launch_l2l2(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *L,
+                 hipStream_t s) {
+  if (nbox <= 0) return;
+  dim3 grid((nbox + 3) / 4, nrhs);
+  if (t.KP == 16) hipLaunchKernelGGL(l2l2_mfma_kernel<16>, grid, dim3(256), 0, s, t, g, boxes, nbox, L);
+  else if (t.KP == 32) hipLaunchKernelGGL(l2l2_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, boxes, nbox, L);
+  else hipLaunchKernelGGL(l2l2_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, boxes, nbox, L);
 }
 void launch_m2l(const DevTables &t, const DevTree &g, int nrhs, const double *M, double *L, hipStream_t s) {
   // blocks of contiguous parent ranges, plus one for the root

@@ -356,24 +356,25 @@ def test_forest_equals_separate_trees(ctx8, flags):
 # ------------------------------------------------------ schedule tuning
 @pytest.mark.parametrize("flags", [B.BX_FP64, B.BX_SPLIT_INT8], ids=["fp64", "split"])
 def test_tuning_changes_no_result(ctx8, flags):
-    # The scheduling parameters only move work between blocks: every output is
-    # summed in the same order, so results are bitwise equal for any setting,
-    # including the extremes (every tile split by rows, none split, one M2L block).
+    # The scheduling parameters only move work between blocks and launches:
+    # every output is summed in the same order, so results are bitwise equal
+    # for any setting, including the extremes (every tile split by rows, none
+    # split, one M2L block, every level alone or two levels per launch).
     torch = _torch()
     ctx = ctx8 if flags == B.BX_FP64 else B.Context(8, 30, flags)
     t, src = I.workload("gauss20_s0")
     f = torch.from_numpy(I.sample(t, src, 8)).cuda()
     tr = B.Tree.from_inputs(ctx, t)
-    assert tr.tuning() == (1.25, 4.0, 1024)
+    assert tr.tuning() == (1.25, 4.0, 1024, 512)
     V0, G0 = B.volume_eval_grad(ctx, tr, f)
-    for heavy, w, blocks in [(1e-3, 1.0, 1), (1e30, 16.0, 7), (0.5, 0.25, 4096)]:
-        tr.set_tuning(heavy, w, blocks)
-        assert tr.tuning() == (heavy, w, blocks)
+    for heavy, w, blocks, fuse in [(1e-3, 1.0, 1, 0), (1e30, 16.0, 7, 100000), (0.5, 0.25, 4096, 300)]:
+        tr.set_tuning(heavy, w, blocks, fuse)
+        assert tr.tuning() == (heavy, w, blocks, fuse)
         V, G = B.volume_eval_grad(ctx, tr, f)
-        assert torch.equal(V, V0) and torch.equal(G, G0), (heavy, w, blocks)
+        assert torch.equal(V, V0) and torch.equal(G, G0), (heavy, w, blocks, fuse)
     V, G, best = B.autotune(ctx, tr, f, reps=2)
     print("autotune:", best)
     assert torch.equal(V, V0) and torch.equal(G, G0)
-    assert tr.tuning() == best[:3] and best[3] > 0
+    assert tr.tuning() == best[:4] and best[4] > 0
     V, G = B.volume_eval_grad(ctx, tr, f)
     assert torch.equal(V, V0) and torch.equal(G, G0)
