@@ -332,6 +332,40 @@ def forest(count: int, seed: int = 0, n: int = 8, workers: int = 16):
     return [t for t, _ in out], [s for _, s in out]
 
 
+def _polar_curve(theta, c0, cos_terms, sin_terms):
+    r = np.full_like(theta, c0)
+    for j, c in cos_terms.items():
+        r = r + c * np.cos(j * theta)
+    for j, d in sin_terms.items():
+        r = r + d * np.sin(j * theta)
+    return r
+
+
+def paper_domain(x, y):
+    """Indicator of the multiply connected domain of the paper's section 6: the
+    region between two polar curves r(theta) = c0 + sum_j (c_j cos j theta +
+    d_j sin j theta), the outer with c0 = 0.25, d3 = c6 = c8 = c10 = 0.01,
+    c5 = 0.02, the inner with c0 = 0.05, c2 = d3 = c5 = c7 = 0.005."""
+    x, y = np.asarray(x, np.float64), np.asarray(y, np.float64)
+    r, th = np.hypot(x, y), np.arctan2(y, x)
+    outer = _polar_curve(th, 0.25, {5: 0.02, 6: 0.01, 8: 0.01, 10: 0.01}, {3: 0.01})
+    inner = _polar_curve(th, 0.05, {2: 0.005, 5: 0.005, 7: 0.005}, {3: 0.005})
+    return (r < outer) & (r > inner)
+
+
+def paper_example_rhs(example: int):
+    """f = Laplacian of the exact solutions of the paper's Examples 1 and 2
+    (u = sin(10(x1 + x2)) + x1^2 - 3 x2 + 8, plus exp(-500 x1^2) in Example 2)
+    inside the domain, extended by zero outside it."""
+    def f(x, y):
+        x, y = np.asarray(x, np.float64), np.asarray(y, np.float64)
+        v = -200.0 * np.sin(10.0 * (x + y)) + 2.0
+        if example == 2:
+            v = v + (1e6 * x * x - 1000.0) * np.exp(-500.0 * x * x)
+        return np.where(paper_domain(x, y), v, 0.0)
+    return f
+
+
 def refine_net_init(seed: int) -> np.ndarray:
     """Initial parameters of the refinement network (flat: W1[128][288], b1[128],
     W2[128][128], b2[128], w3[128], b3[1]): He-uniform weights (bound
@@ -348,7 +382,10 @@ def refine_net_init(seed: int) -> np.ndarray:
 
 def workload(name: str, n: int = 8):
     """The named synthetic workloads: returns (tree, source function), or for a
-    forest (forest<count>_s<seed>) (list of trees, list of sources)."""
+    forest (forest<count>_s<seed>) (list of trees, list of sources).  The
+    paper<d>_ex<k> workloads are the uniform depth-d trees of the paper's box-code
+    tables with Example k's right-hand side extended by zero (use n = 4 for the
+    paper's node count)."""
     if name.startswith("forest"):
         body = name[len("forest"):]
         count, seed = (int(body.split("_s")[0]), int(body.split("_s")[1])) if "_s" in body else (int(body), 0)
@@ -365,4 +402,7 @@ def workload(name: str, n: int = 8):
     if name.startswith("kink"):
         cap = int(name.split("_cap")[1]) if "_cap" in name else 16
         return adaptive_tree(kink_source, n, 1e-10, cap), kink_source
+    if name.startswith("paper"):                     # paper<depth>_ex<1|2>: the paper's uniform-tree rows
+        depth, ex = name[len("paper"):].split("_ex")
+        return uniform_tree(int(depth)), paper_example_rhs(int(ex))
     raise KeyError(name)

@@ -378,3 +378,26 @@ def test_tuning_changes_no_result(ctx8, flags):
     assert tr.tuning() == best[:4] and best[4] > 0
     V, G = B.volume_eval_grad(ctx, tr, f)
     assert torch.equal(V, V0) and torch.equal(G, G0)
+
+
+# ------------------------------------------- the paper's own right-hand sides
+@pytest.mark.parametrize("example", [1, 2])
+def test_paper_examples_zero_extension_n4(example):
+    # The paper's node count (4 x 4) on a uniform tree, with Example 1 or 2's
+    # f = Laplacian(u) inside its multiply connected domain and zero outside
+    # (a discontinuous source: the box code integrates the piecewise
+    # polynomial f~ whatever f is), against the oracle on sampled leaves.
+    torch = _torch()
+    t, src = I.workload(f"paper4_ex{example}", 4)
+    f = I.sample(t, src, 4)
+    ctx = B.Context(4, 30, B.BX_FP64)
+    tr = B.Tree.from_inputs(ctx, t)
+    V, G = B.volume_eval_grad(ctx, tr, torch.from_numpy(f).cuda())
+    V, G = V.cpu().numpy()[0], G.cpu().numpy()[0]
+    sel = np.sort(np.random.default_rng(example).choice(t.n_leaves, 24, replace=False))
+    Vo, Gxo, Gyo = oracle.volume_at_nodes(t.level, t.ix, t.iy, f, leaves=sel)
+    ev = np.abs(V[sel] - Vo).max() / np.abs(V).max()
+    ex = np.abs(G[sel, 0] - Gxo).max() / np.abs(G[:, 0]).max()
+    ey = np.abs(G[sel, 1] - Gyo).max() / np.abs(G[:, 1]).max()
+    print(f"example {example}, n = 4, 24 of {t.n_leaves} leaves: E(V)={ev:.2e} E(dV/dx1)={ex:.2e} E(dV/dx2)={ey:.2e}")
+    assert ev < TOL and ex < TOL and ey < TOL
