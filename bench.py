@@ -262,10 +262,15 @@ def main():
     learned = None
     if args.workload.startswith("learned"):          # trees proposed by the trained network
         tree, src, learned = learned_forest(int(args.workload[7:] or 256), args.n)
+    elif args.workload.startswith("forest"):         # trees and their samples from one process pool
+        body = args.workload[len("forest"):]
+        count, seed = (int(body.split("_s")[0]), int(body.split("_s")[1])) if "_s" in body else (int(body), 0)
+        tree, src, fs = I.forest(count, seed, args.n, samples=True)
     else:
         tree, src = I.workload(args.workload, args.n)
     if isinstance(tree, list):                       # a forest: one upload, one evaluation
-        f_host = np.concatenate([I.sample(t, s_, args.n) for t, s_ in zip(tree, src)])
+        f_host = (np.concatenate(fs) if args.workload.startswith("forest")
+                  else np.concatenate([I.sample(t, s_, args.n) for t, s_ in zip(tree, src)]))
         tree = Forest(tree)
     elif args.nrhs > 1:                              # the same tree, n_rhs seeded sources
         f_host = np.stack([I.sample(tree, I.random_gaussians(1000 + r, 20), args.n) for r in range(args.nrhs)])

@@ -311,25 +311,30 @@ def is_balanced(tree: Tree) -> bool:
 
 
 def _forest_tree(args):
-    k, seed, n = args
+    k, seed, n, with_samples = args
     r = np.random.default_rng([seed, k])
     K, cap = int(r.integers(1, 41)), int(r.integers(6, 13))
     src = random_gaussians(100000 * seed + k, K)
-    return gaussian_tree(src, n, 1e-10, cap), src
+    t = gaussian_tree(src, n, 1e-10, cap)
+    return t, src, (sample(t, src, n) if with_samples else None)
 
 
-def forest(count: int, seed: int = 0, n: int = 8, workers: int = 16):
+def forest(count: int, seed: int = 0, n: int = 8, workers: int = 16, samples: bool = False):
     """`count` trees of uneven depth: tree k draws its Gaussian count in [1, 40] and
     its depth cap in [6, 12] from a generator seeded by (seed, k), and its sources
-    like the 20-Gaussian workload (seed 100000 seed + k); built in a process pool."""
+    like the 20-Gaussian workload (seed 100000 seed + k); built in a process pool.
+    Returns (trees, sources), or with samples=True (trees, sources, samples of each
+    tree at its n x n nodes), the sampling done in the same pool."""
     import multiprocessing as mp
-    jobs = [(k, seed, n) for k in range(count)]
+    jobs = [(k, seed, n, samples) for k in range(count)]
     if workers > 1 and count > 1:
         with mp.get_context("fork").Pool(min(workers, count)) as pool:
             out = pool.map(_forest_tree, jobs)
     else:
         out = [_forest_tree(j) for j in jobs]
-    return [t for t, _ in out], [s for _, s in out]
+    if samples:
+        return [o[0] for o in out], [o[1] for o in out], [o[2] for o in out]
+    return [o[0] for o in out], [o[1] for o in out]
 
 
 def _polar_curve(theta, c0, cos_terms, sin_terms):

@@ -401,3 +401,56 @@ def test_paper_examples_zero_extension_n4(example):
     ey = np.abs(G[sel, 1] - Gyo).max() / np.abs(G[:, 1]).max()
     print(f"example {example}, n = 4, 24 of {t.n_leaves} leaves: E(V)={ev:.2e} E(dV/dx1)={ex:.2e} E(dV/dx2)={ey:.2e}")
     assert ev < TOL and ex < TOL and ey < TOL
+
+
+# ------------------------------------------- full-size workloads, sampled
+def _sampled_check(t, f, V, G, sel, tol, label):
+    Vo, Gxo, Gyo = oracle.volume_at_nodes(t.level, t.ix, t.iy, f, leaves=sel, cx=t.cx, cy=t.cy, width=t.width)
+    ev = np.abs(V[sel] - Vo).max() / np.abs(V).max()
+    ex = np.abs(G[sel, 0] - Gxo).max() / np.abs(G[:, 0]).max()
+    ey = np.abs(G[sel, 1] - Gyo).max() / np.abs(G[:, 1]).max()
+    print(f"{label}: {len(sel)} of {t.n_leaves} leaves: E(V)={ev:.2e} E(dV/dx1)={ex:.2e} E(dV/dx2)={ey:.2e}")
+    assert ev < tol and ex < tol and ey < tol
+
+
+@pytest.mark.parametrize("name,n", [("kink_cap16", 8), ("kink_cap12", 16)])
+def test_kink_source_full_size_sampled(name, n):
+    # Configuration 3 at its full size (the C0 kink source, refinement to the
+    # cap along the curve), both precisions in the launch configuration the
+    # benchmark times, on leaves the oracle evaluates one by one: the deepest
+    # leaf nearest the kink, the coarsest leaf, and two at random.
+    torch = _torch()
+    t, src = I.workload(name, n)
+    f = I.sample(t, src, n)
+    deep = np.flatnonzero(t.level == t.level.max())
+    rng = np.random.default_rng(3)
+    sel = np.unique(np.concatenate([deep[:1], [int(np.argmin(t.level))], rng.choice(t.n_leaves, 2, replace=False)]))
+    fd = torch.from_numpy(f).cuda()
+    for flags, tol in ((B.BX_FP64, TOL), (B.BX_SPLIT_INT8, SPLIT_TOL)):
+        ctx = B.Context(n, 30, flags)
+        tr = B.Tree.from_inputs(ctx, t)
+        V, G = B.volume_eval_grad(ctx, tr, fd)
+        V, G = V.cpu().numpy()[0], G.cpu().numpy()[0]
+        _sampled_check(t, f, V, G, sel, tol, f"{name} n={n} {'split' if flags else 'fp64'}")
+        del V, G, tr, ctx
+
+
+def test_forest256_full_size_sampled():
+    # Configuration 4's forest at its full size (256 trees, 1-40 Gaussians,
+    # depth caps 6-12) as one structure, mixed precision; trees do not
+    # interact, so sampled leaves of a few trees are checked against the
+    # oracle on their own tree.
+    torch = _torch()
+    trees, srcs, fs = I.forest(256, 0, 8, workers=8, samples=True)   # host processes (no GPU use)
+    ctx = B.Context(8, 30, B.BX_SPLIT_INT8)
+    forest = B.Tree.forest(ctx, trees)
+    V, G = B.volume_eval_grad(ctx, forest, torch.from_numpy(np.concatenate(fs)).cuda())
+    V, G = V.cpu().numpy()[0], G.cpu().numpy()[0]
+    off = np.concatenate([[0], np.cumsum([t.n_leaves for t in trees])])
+    depth = [int(t.level.max()) for t in trees]
+    rng = np.random.default_rng(11)
+    for k in sorted({int(np.argmax(depth)), int(np.argmin(depth)), int(rng.integers(len(trees)))}):
+        t, sl = trees[k], slice(off[k], off[k + 1])
+        sel = np.unique(np.concatenate([np.flatnonzero(t.level == t.level.max())[:1],
+                                        rng.choice(t.n_leaves, min(2, t.n_leaves), replace=False)]))
+        _sampled_check(t, fs[k], V[sl], G[sl], sel, SPLIT_TOL, f"forest256 tree {k} (depth {depth[k]})")
