@@ -252,7 +252,7 @@ def main():
                           "launches": 5}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for {args.gpus}); "
               "the multi-GPU sharding is a design, not code.", file=sys.stderr)
         sys.exit(2)
 

@@ -270,7 +270,7 @@ const char *bx_last_error(void);
 
 /* ------------------------------------------------------------------------
  * Learned refinement (the adaptive refinement of section 3.1 proposed by a
- * small network; the plain tail criterion still judges every leaf).
+ * small network; the plain tail criterion still checks every leaf).
  *
  * A perceptron 288 -> 128 -> 128 -> 1 (ReLU) proposes whether a quadtree box
  * is split.  Its inputs are features of the box (bx_mlp_features); its

@@ -5,7 +5,7 @@ may import this module.  It shares no code with the HIP library.
 
 The network proposes the split / no-split decision of a quadtree box from
 samples of the source on the box (the refinement of section 3.1, whose plain
-criterion stays the judge of every leaf).  Everything here is written out in
+criterion still checks every leaf).  Everything here is written out in
 FP64 from the definitions:
 
 * features x[288] of a box from its samples s on a 16 x 16 grid of

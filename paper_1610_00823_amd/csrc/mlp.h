@@ -1,7 +1,7 @@
 // Refinement network: a 288 -> 128 -> 128 -> 1 perceptron that proposes the
 // split / no-split decision of a quadtree box from samples of the source on
 // the box (the adaptive refinement of section 3.1; the plain tail criterion
-// still judges every leaf).  BF16 operands on the matrix cores, FP32 sums,
+// still checks every leaf).  BF16 operands on the matrix cores, FP32 sums,
 // FP32 master parameters and Adam moments.
 #pragma once
 #include <hip/hip_runtime.h>
