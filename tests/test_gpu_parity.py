@@ -454,3 +454,51 @@ def test_forest256_full_size_sampled():
         sel = np.unique(np.concatenate([np.flatnonzero(t.level == t.level.max())[:1],
                                         rng.choice(t.n_leaves, min(2, t.n_leaves), replace=False)]))
         _sampled_check(t, fs[k], V[sl], G[sl], sel, SPLIT_TOL, f"forest256 tree {k} (depth {depth[k]})")
+
+
+# ------------------------------------------------------------ edge cases
+@pytest.mark.parametrize("flags", [B.BX_FP64, B.BX_SPLIT_INT8], ids=["fp64", "split"])
+def test_zero_and_single_leaf_sources(ctx8, flags):
+    # f = 0 gives exactly zero (the mixed path's scales come from max|f|); a
+    # source on one leaf of a graded tree matches the oracle, which sums that
+    # leaf alone: FP64 relative to the largest value, the mixed path within its
+    # slice tolerance, which is relative to ||f||_inf W^2 (V) and ||f||_inf W
+    # (grad V), W = 1 (one deep leaf makes max|V| far smaller than that).
+    torch = _torch()
+    ctx = ctx8 if flags == B.BX_FP64 else B.Context(8, 30, flags)
+    t = I.point_refined_tree([[0.3, 0.2], [-0.26, -0.4]], [5, 3])
+    tr = B.Tree.from_inputs(ctx, t)
+    V, G = B.volume_eval_grad(ctx, tr, torch.zeros((1, t.n_leaves, 8, 8), dtype=torch.float64, device="cuda"))
+    assert torch.count_nonzero(V).item() == 0 and torch.count_nonzero(G).item() == 0
+    f = np.zeros((t.n_leaves, 8, 8))
+    k = int(np.argmax(t.level))
+    f[k] = np.random.default_rng(8).standard_normal((8, 8))
+    V, G = B.volume_eval_grad(ctx, tr, torch.from_numpy(f).cuda())
+    V, G = V.cpu().numpy()[0], G.cpu().numpy()[0]
+    assert np.all(np.isfinite(V)) and np.all(np.isfinite(G))
+    sel = np.array([0, k, t.n_leaves - 1])
+    if flags == B.BX_FP64:
+        check_vs_oracle(t, f, V, G, leaves=sel)
+    else:
+        Vo, Gxo, Gyo = oracle.volume_at_nodes(t.level, t.ix, t.iy, f, leaves=sel)
+        fm = np.abs(f).max()
+        ev = np.abs(V[sel] - Vo).max() / fm
+        eg = max(np.abs(G[sel, 0] - Gxo).max(), np.abs(G[sel, 1] - Gyo).max()) / fm
+        print(f"single-leaf source, mixed: |dV| / ||f|| = {ev:.2e}, |dG| / ||f|| = {eg:.2e}")
+        assert ev < SPLIT_TOL and eg < SPLIT_TOL
+
+
+@pytest.mark.parametrize("flags", [B.BX_FP64, B.BX_SPLIT_INT8], ids=["fp64", "split"])
+def test_power_of_two_scaling_is_exact(ctx8, flags):
+    # Every operation is linear in f and every scale the mixed path chooses is
+    # a power of two taken from max|f|, so 2^k f gives exactly 2^k V and 2^k grad V.
+    torch = _torch()
+    ctx = ctx8 if flags == B.BX_FP64 else B.Context(8, 30, flags)
+    t, src = I.workload("uniform4_gauss")
+    f = I.sample(t, src, 8)
+    tr = B.Tree.from_inputs(ctx, t)
+    V0, G0 = B.volume_eval_grad(ctx, tr, torch.from_numpy(f).cuda())
+    for k in (-300, -7, 9, 250):
+        V, G = B.volume_eval_grad(ctx, tr, torch.from_numpy(np.ldexp(f, k)).cuda())
+        assert torch.equal(V, V0 * 2.0 ** k), k          # 2.0 ** k is exact
+        assert torch.equal(G, G0 * 2.0 ** k), k
