@@ -383,26 +383,28 @@ __global__ void __launch_bounds__(256) p2m_mfma_kernel(DevTables t, DevTree g, c
 // ------------------------------------------------------------------ M2L
 // b~_l = sum_s (d/2)^-l [H y(s)]_l + [l = 0] sum_s a_0 (log h + log|d|),
 // y_k = a~_k (-d/2)^-k, for the V list of each box.  H (KP x KP, real, the same
-// for every offset) stays in registers as MFMA A fragments; the B columns are
-// (source, Re/Im) pairs, 8 sources per 16 columns.  The V lists of the four
-// children of an internal box P (one wave each) all come from the 6 x 6 grid of
-// boxes below P's neighbourhood, whose multipoles are staged in LDS (rows
-// padded so that the 8 sources of a column group hit distinct banks).  Each
-// block keeps the power tables of the 49 offsets in LDS and works through a
-// contiguous range of parents, with the next parent's grid requested while the
-// current one is multiplied.  Writes (initialises) every box's local
-// expansion; the last block writes the roots' zero expansions.
+// for every offset) is the MFMA A operand; the B columns are (source, Re/Im)
+// pairs, 8 sources per 16 columns.  The V lists of the four children of an
+// internal box P (one wave each) all come from the 6 x 6 grid of boxes below
+// P's neighbourhood, whose multipoles are staged in LDS (rows padded so that
+// the 8 sources of a column group hit distinct banks).  Each block keeps H and
+// the power table of the 49 offsets in LDS (the target powers (d/2)^-l are
+// (-1)^l times the source powers), which leaves room for three blocks per CU,
+// and works through a contiguous range of parents, with the next parent's grid
+// and V entries requested while the current one is multiplied.  Writes
+// (initialises) every box's local expansion; the last block writes the roots'
+// zero expansions.
 constexpr int M2L_BLOCKS = 1024;
 
-
 template <int KPT>
-__global__ void __launch_bounds__(256, KPT <= 32 ? 2 : 1) m2l_mfma_kernel(DevTables t, DevTree g,
+__global__ void __launch_bounds__(256, KPT <= 32 ? 3 : 1) m2l_mfma_kernel(DevTables t, DevTree g,
                                                                                const double *__restrict__ M,
                                                                                double *__restrict__ L, int per_block) {
   constexpr int MT = KPT / 16, KS = KPT / 4;
   constexpr int PWS = KPT + 1;                 // padded rows: 8 offsets / sources per column group, distinct banks
   constexpr int GPT = (36 * KPT + 255) / 256;  // grid coefficients per thread
-  __shared__ double2 spw[2][NOFF_DEV * PWS];
+  __shared__ double2 spw[NOFF_DEV * PWS];     // (-d/2)^-k; the target powers (d/2)^-l are (-1)^l times these
+  __shared__ double sH[KPT * (KPT + 1)];      // the core, rows padded
   __shared__ double2 sM[36 * PWS];
   __shared__ double slogd[NOFF_DEV];
   const int rhs = blockIdx.y;
@@ -419,15 +421,10 @@ __global__ void __launch_bounds__(256, KPT <= 32 ? 2 : 1) m2l_mfma_kernel(DevTab
   if (p0 >= p1) return;                        // whole block: no barrier is skipped
   const double *Mr = M + (size_t)rhs * g.n_boxes * KPT * 2;
   for (int i = threadIdx.x; i < NOFF_DEV * KPT; i += 256) {
-    spw[0][i / KPT * PWS + i % KPT] = ((const double2 *)t.pw_src)[i];
-    spw[1][i / KPT * PWS + i % KPT] = ((const double2 *)t.pw_tgt)[i];
+    spw[i / KPT * PWS + i % KPT] = ((const double2 *)t.pw_src)[i];
   }
   if (threadIdx.x < NOFF_DEV) slogd[threadIdx.x] = t.logd[threadIdx.x];
-  double hA[MT][KS];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) hA[m][ks] = t.H[(size_t)(m * 16 + col) * KPT + kq * KS + ks];
+  for (int i = threadIdx.x; i < KPT * KPT; i += 256) sH[i / KPT * (KPT + 1) + i % KPT] = t.H[i];
   // this thread's share of a parent's grid: coefficient i = threadIdx.x + 256 j;
   // this lane's V entries (iteration it: entry 8 it + col/2 of its wave's
   // child) and the parent's first child and level, all requested one parent
@@ -476,7 +473,7 @@ __global__ void __launch_bounds__(256, KPT <= 32 ? 2 : 1) m2l_mfma_kernel(DevTab
       const int s_c = ok ? ent[it] & 255 : 0, o_c = ok ? ent[it] >> 8 : 0;
       double bv[KS];
       const double2 *ap = &sM[s_c * PWS + kq * KS];
-      const double2 *wp = &spw[0][o_c * PWS + kq * KS];
+      const double2 *wp = &spw[o_c * PWS + kq * KS];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const double2 a = ap[ks], w = wp[ks];
@@ -490,8 +487,9 @@ __global__ void __launch_bounds__(256, KPT <= 32 ? 2 : 1) m2l_mfma_kernel(DevTab
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-        for (int m = 0; m < MT; ++m) c[m] = mfma4(hA[m][ks], bv[ks], c[m]);
-      const double2 *qp = &spw[1][o_c * PWS];
+        for (int m = 0; m < MT; ++m) c[m] = mfma4(sH[(m * 16 + col) * (KPT + 1) + kq * KS + ks], bv[ks], c[m]);
+      const double2 *qp = &spw[o_c * PWS];
+      const double sg = (kq & 1) ? -1.0 : 1.0;     // (-1)^l, l = m 16 + 4 r + kq
 #pragma unroll
       for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -500,18 +498,14 @@ __global__ void __launch_bounds__(256, KPT <= 32 ? 2 : 1) m2l_mfma_kernel(DevTab
           const double zr = part ? zo : z, zi = part ? z : zo;
           const double2 q = qp[m * 16 + 4 * r + kq];
           const double v = part ? zr * q.y + zi * q.x : zr * q.x - zi * q.y;
-          acc[m][r] += ok ? v : 0.0;
+          acc[m][r] += ok ? sg * v : 0.0;
         }
     };
-    // entries are packed from the front: group it is live when its first entry
-    // is.  Groups run in pairs with no branch between them, so that one's
-    // products overlap the other's operand building (a dead second group adds
-    // zeros); the launch bound keeps two waves per SIMD.
+    // entries are packed from the front: group it is live when its first entry is
 #pragma unroll
-    for (int it = 0; it < 4; it += 2) {
+    for (int it = 0; it < 4; ++it) {
       if (__builtin_amdgcn_readfirstlane(ent[it]) < 0) break;
       group(it);
-      group(it + 1);
     }
     // sum over the 8 sources of each column group (lanes with equal kq and part)
 #pragma unroll
