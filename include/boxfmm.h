@@ -206,10 +206,10 @@ int bx_split_tolerance(bx_ctx *ctx, double tol);
  *   tune[0] heavy-tile threshold: a near tile whose cost exceeds this multiple
  *           of the balanced per-block share is split by rows (default 1.25);
  *   tune[1] split contexts: cost of one FP64 slot of the near kernel, in int8
- *           slice pairs, for that balance (default 4);
- *   tune[2] persistent M2L blocks (default 1024);
+ *           slice pairs, for that balance (default 16);
+ *   tune[2] persistent M2L blocks (default 4096);
  *   tune[3] M2M and L2L run two levels per launch where the middle level has
- *           at most this many internal boxes (default 512; 0: never).
+ *           at most this many internal boxes (default 0: never).
  * bx_tree_tuning sets them (tune[0..2] <= 0 or tune[3] = -1 keeps the current
  * value), rebuilds the work lists on the device (allocates; synchronizes
  * `stream`) and drops captured evaluation graphs.  bx_tree_tuning_get copies

@@ -61,9 +61,9 @@ struct bx_tree {
   bool split = false;
   std::vector<void *> unit_bufs;       // device work-unit arrays
   double tune_heavy = 1.25;            // heavy-tile threshold, in balanced shares of a resident block
-  double tune_f64_weight = 4.0;        // split kernel: an FP64 slot's cost in int8 slice pairs
-  int tune_m2l_blocks = 1024;          // persistent M2L blocks
-  int tune_fuse = 512;                // two-level M2M / L2L launches when the middle level has at most this many internal boxes
+  double tune_f64_weight = 16.0;       // split kernel: an FP64 slot's cost in int8 slice pairs
+  int tune_m2l_blocks = 4096;          // persistent M2L blocks
+  int tune_fuse = 0;                // two-level M2M / L2L launches when the middle level has at most this many internal boxes
 };
 
 struct bx_mlp {
@@ -320,19 +320,33 @@ static int upload_units(bx_ctx *ctx, bx_tree *t, hipStream_t s) {
     }
     order_units(nu, nunit_tile, nunit_mt);
   }
-  for (void *p : t->unit_bufs) (void)hipFree(p);
-  t->unit_bufs.clear();
-  DevTree &g = t->dg;
+  // upload the new lists first; the old ones stay in use until all copies succeeded
+  std::vector<void *> bufs;
+  const int *ut = nullptr, *um = nullptr, *nt = nullptr, *nm = nullptr;
   int rc;
-  if ((rc = upload(t->unit_bufs, unit_tile, &g.unit_tile, s)) || (rc = upload(t->unit_bufs, unit_mt, &g.unit_mt, s)) ||
-      (rc = upload(t->unit_bufs, nunit_tile, &g.nunit_tile, s)) || (rc = upload(t->unit_bufs, nunit_mt, &g.nunit_mt, s)))
+  if ((rc = upload(bufs, unit_tile, &ut, s)) || (rc = upload(bufs, unit_mt, &um, s)) ||
+      (rc = upload(bufs, nunit_tile, &nt, s)) || (rc = upload(bufs, nunit_mt, &nm, s))) {
+    (void)hipStreamSynchronize(s);
+    for (void *p : bufs) (void)hipFree(p);
     return rc;
+  }
+  // the host vectors die here: the copies must have completed
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    for (void *p : bufs) (void)hipFree(p);
+    return hip_fail(e, "upload_units");
+  }
+  for (void *p : t->unit_bufs) (void)hipFree(p);
+  t->unit_bufs.swap(bufs);
+  DevTree &g = t->dg;
+  g.unit_tile = ut;
+  g.unit_mt = um;
+  g.nunit_tile = nt;
+  g.nunit_mt = nm;
   g.n_units = (int)unit_tile.size();
   g.n_nunits = (int)nunit_tile.size();
   g.m2l_blocks = t->tune_m2l_blocks;
-  // the host vectors die here: the copies must have completed
-  hipError_t e = hipStreamSynchronize(s);
-  return e == hipSuccess ? BX_OK : hip_fail(e, "upload_units");
+  return BX_OK;
 }
 
 int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree **out, bx_stream_t stream) {
@@ -800,12 +814,21 @@ int bx_tree_tuning(bx_ctx *ctx, bx_tree *tree, const double tune[4], bx_stream_t
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipStreamSynchronize(s);   // no evaluation may still read the old work lists
   if (e != hipSuccess) return hip_fail(e, "bx_tree_tuning");
+  const double old_heavy = tree->tune_heavy, old_w = tree->tune_f64_weight;
+  const int old_blocks = tree->tune_m2l_blocks, old_fuse = tree->tune_fuse;
   if (tune[0] > 0) tree->tune_heavy = tune[0];
   if (tune[1] > 0) tree->tune_f64_weight = tune[1];
   if (tune[2] > 0) tree->tune_m2l_blocks = (int)tune[2];
   if (tune[3] >= 0) tree->tune_fuse = (int)tune[3];   // -1 keeps it; 0 turns two-level launches off
   drop_graphs(tree);
-  return upload_units(ctx, tree, s);
+  const int rc = upload_units(ctx, tree, s);
+  if (rc) {                                            // the old work lists are still in place
+    tree->tune_heavy = old_heavy;
+    tree->tune_f64_weight = old_w;
+    tree->tune_m2l_blocks = old_blocks;
+    tree->tune_fuse = old_fuse;
+  }
+  return rc;
 }
 
 int bx_tree_tuning_get(const bx_tree *tree, double tune[4]) {
@@ -852,16 +875,17 @@ int bx_autotune(bx_ctx *ctx, bx_tree *tree, const double *f, int nrhs, double *V
     return BX_OK;
   };
   double cur[4] = {tree->tune_heavy, tree->tune_f64_weight, (double)tree->tune_m2l_blocks, (double)tree->tune_fuse};
+  const double start[4] = {cur[0], cur[1], cur[2], cur[3]};
   double best_ms = 0;
   int rc = bx_tree_tuning(ctx, tree, cur, stream);
   if (!rc) rc = time_it(&best_ms);
-  static const double cand_m2l[] = {256, 512, 768, 1024, 1536, 2048};
+  static const double cand_m2l[] = {1024, 2048, 3072, 4096, 6144, 8192};
   static const double cand_heavy[] = {0.75, 1.0, 1.25, 1.5, 2.0, 1e30};
-  static const double cand_w[] = {1, 2, 4, 8, 16};
-  static const double cand_fuse[] = {0, 512, 2048, 8192};
+  static const double cand_w[] = {2, 4, 8, 16, 32, 64};
+  static const double cand_fuse[] = {0, 512, 2048};
   struct Axis { int k; const double *v; int n; };
-  const Axis axes[4] = {{2, cand_m2l, 6}, {0, cand_heavy, 6}, {1, cand_w, (ctx->flags & BX_SPLIT_INT8) ? 5 : 0},
-                        {3, cand_fuse, 4}};
+  const Axis axes[4] = {{2, cand_m2l, 6}, {0, cand_heavy, 6}, {1, cand_w, (ctx->flags & BX_SPLIT_INT8) ? 6 : 0},
+                        {3, cand_fuse, 3}};
   for (const Axis &a : axes) {
     for (int i = 0; i < a.n && !rc; ++i) {
       if (a.v[i] == cur[a.k]) continue;
@@ -874,7 +898,11 @@ int bx_autotune(bx_ctx *ctx, bx_tree *tree, const double *f, int nrhs, double *V
       }
     }
   }
-  // leave the best setting in place, with its result in V and G
+  // leave the best setting in place, with its result in V and G (on failure,
+  // the setting the tuner started from)
+  if (rc) {
+    (void)bx_tree_tuning(ctx, tree, start, stream);
+  }
   if (!rc) rc = bx_tree_tuning(ctx, tree, cur, stream);
   if (!rc) rc = bx_volume_eval_grad(ctx, tree, f, nrhs, V, G, stream);
   if (!rc) {
