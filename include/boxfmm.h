@@ -204,7 +204,8 @@ int bx_split_tolerance(bx_ctx *ctx, double tol);
  * Scheduling parameters of a tree's evaluation (none changes any result: every
  * output is summed in the same order whatever they are):
  *   tune[0] heavy-tile threshold: a near tile whose cost exceeds this multiple
- *           of the balanced per-block share is split by rows (default 1.25);
+ *           of the balanced per-block share is split by rows (default 1.0,
+ *           split contexts 1.5);
  *   tune[1] split contexts: cost of one FP64 slot of the near kernel, in int8
  *           slice pairs, for that balance (default 16);
  *   tune[2] persistent M2L blocks (default 4096);

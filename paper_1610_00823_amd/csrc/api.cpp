@@ -60,7 +60,7 @@ struct bx_tree {
   std::vector<int> h_tile_ptr, h_nslot_ptr, h_tile_nsl;
   bool split = false;
   std::vector<void *> unit_bufs;       // device work-unit arrays
-  double tune_heavy = 1.25;            // heavy-tile threshold, in balanced shares of a resident block
+  double tune_heavy = 1.0;             // heavy-tile threshold, in balanced shares of a resident block (1.5 split)
   double tune_f64_weight = 16.0;       // split kernel: an FP64 slot's cost in int8 slice pairs
   int tune_m2l_blocks = 4096;          // persistent M2L blocks
   int tune_fuse = 0;                // two-level M2M / L2L launches when the middle level has at most this many internal boxes
@@ -481,6 +481,7 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
   t->h_nslot_ptr = nslot_ptr;
   t->h_tile_nsl = tile_nsl;
   t->split = split;
+  t->tune_heavy = (ctx->flags & BX_SPLIT_INT8) ? 1.5 : 1.0;   // the measured best of each leaf kernel
   g.split_sf = split_sf;
   t->split_sf = split_sf;
   // X-list tiles: target boxes with X entries, sorted by configuration set

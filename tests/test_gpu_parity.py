@@ -365,7 +365,7 @@ def test_tuning_changes_no_result(ctx8, flags):
     t, src = I.workload("gauss20_s0")
     f = torch.from_numpy(I.sample(t, src, 8)).cuda()
     tr = B.Tree.from_inputs(ctx, t)
-    assert tr.tuning() == (1.25, 16.0, 4096, 0)
+    assert tr.tuning() == (1.5 if flags == B.BX_SPLIT_INT8 else 1.0, 16.0, 4096, 0)
     V0, G0 = B.volume_eval_grad(ctx, tr, f)
     for heavy, w, blocks, fuse in [(1e-3, 1.0, 1, 0), (1e30, 16.0, 7, 100000), (0.5, 0.25, 4096, 300)]:
         tr.set_tuning(heavy, w, blocks, fuse)

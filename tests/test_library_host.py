@@ -419,7 +419,7 @@ def test_tuning_parameters_host_side():
     # Defaults and argument checks of the schedule setters (no evaluation on the CPU).
     ctx = B.Context(8, 16, B.BX_FP64 | B.BX_HOST_ONLY)
     tr = B.Tree.from_inputs(ctx, I.uniform_tree(2))
-    assert tr.tuning() == (1.25, 16.0, 4096, 0)
+    assert tr.tuning() == (1.0, 16.0, 4096, 0)
     for blocks in (2.5, 70000):
         with pytest.raises(B.BoxFMMError) as e:
             tr.set_tuning(m2l_blocks=blocks)
@@ -430,6 +430,6 @@ def test_tuning_parameters_host_side():
     with pytest.raises(B.BoxFMMError) as e:
         tr.set_tuning(fuse=-2)
     assert e.value.code == B.BX_E_ARG
-    assert tr.tuning() == (1.25, 16.0, 4096, 0)
+    assert tr.tuning() == (1.0, 16.0, 4096, 0)
     rc = B.lib().bx_autotune(ctx._h, tr._h, None, 1, None, None, 1, None, None)
     assert rc == B.BX_E_ARG
