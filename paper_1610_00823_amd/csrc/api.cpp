@@ -43,6 +43,7 @@ struct bx_tree {
   int graph_next = 0;
   bx::HostTree H;
   std::vector<int> int_start;            // per level: offset of its internal boxes in int_boxes
+  std::vector<int> int_child_base;       // per level: first child of its internal boxes if contiguous, else -1
   const int *int_boxes = nullptr;        // device
   std::vector<void *> dev;
   bx::DevTree dg{};
@@ -572,6 +573,16 @@ int bx_tree_upload(bx_ctx *ctx, const bx_tree_desc *trees, int n_trees, bx_tree 
       if (H.leaf_of_box[b] < 0) ib.push_back(b);
   }
   t->int_start[H.n_levels] = (int)ib.size();
+  // per level: the first child of the level's internal boxes when the children
+  // are contiguous in list order (4 per box, level-major Morton order), else -1
+  t->int_child_base.assign(H.n_levels, -1);
+  for (int l = 0; l + 1 < H.n_levels; ++l) {
+    const int base = H.level_start[l + 1];
+    bool contiguous = true;
+    for (int i = t->int_start[l]; i < t->int_start[l + 1] && contiguous; ++i)
+      contiguous = H.child0[ib[i]] == base + 4 * (i - t->int_start[l]);
+    t->int_child_base[l] = contiguous ? base : -1;
+  }
   t->n_slots = (int64_t)slot_type.size();
   if (ctx->flags & BX_HOST_ONLY) {
     t->upload_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -683,7 +694,7 @@ static int enqueue_eval(bx_ctx *ctx, bx_tree *t, const double *f, int nrhs, doub
       launch_m2m2(d, g, t->int_boxes + t->int_start[l - 1], n_int(l - 1), nrhs, t->M, s);
       l -= 2;
     } else {
-      launch_m2m(d, g, t->int_boxes + t->int_start[l], n_int(l), nrhs, t->M, s);
+      launch_m2m(d, g, t->int_boxes + t->int_start[l], n_int(l), t->int_child_base[l], nrhs, t->M, s);
       l -= 1;
     }
   }

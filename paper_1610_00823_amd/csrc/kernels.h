@@ -88,8 +88,8 @@ struct DevTree {
 // Expansion storage: [n_rhs][NB][KP] complex (interleaved re, im).
 void launch_p2m(const DevTables &t, const DevTree &g, const double *f, int nrhs, double *M, hipStream_t s);
 // Upward pass step for the internal boxes `boxes` of one level.
-void launch_m2m(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *M,
-                hipStream_t s);
+void launch_m2m(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int child_base, int nrhs,
+                double *M, hipStream_t s);   // child_base: see m2m_mfma_kernel (-1: look children up)
 // two levels per launch: boxes = internal boxes of the upper level
 void launch_m2m2(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *M,
                  hipStream_t s);

@@ -41,15 +41,18 @@ __device__ inline dbl4 mfma4(double a, double b, dbl4 c) {
 // in LDS in a fixed order.
 template <int KPT>
 __global__ void __launch_bounds__(256) m2m_mfma_kernel(DevTables t, DevTree g, const int *__restrict__ boxes,
-                                                       int nbox, double *__restrict__ M) {
+                                                       int nbox, int child_base, double *__restrict__ M) {
+  // child_base >= 0: the children of the i-th box of the list are boxes
+  // child_base + 4 i .. + 3 (level-major Morton order), so their multipoles
+  // are requested without waiting for the box index
   constexpr int R = 2 * KPT, MT = R / 16, KS = R / 4;
   __shared__ double part[4][16][R + 1];
   const int lane = threadIdx.x & 63, c = threadIdx.x >> 6, col = lane & 15, kq = lane >> 4;
   const int i = blockIdx.x * 16 + col, rhs = blockIdx.y;
   const bool ok = i < nbox;
-  const int box = ok ? boxes[i] : 0;
   double *Mr = M + (size_t)rhs * g.n_boxes * R;
-  const double *bp = Mr + (size_t)((ok ? g.child0[box] : 0) + c) * R + kq * KS;
+  const int c0 = !ok ? 0 : (child_base >= 0 ? child_base + 4 * i : g.child0[boxes[i]]);
+  const double *bp = Mr + (size_t)(c0 + c) * R + kq * KS;
   const double *A = t.m2m_frag + (size_t)c * MT * KS * 64;
   dbl4 acc[MT];
 #pragma unroll
@@ -1212,13 +1215,13 @@ void launch_p2m(const DevTables &t, const DevTree &g, const double *f, int nrhs,
   else if (t.KP == 32) hipLaunchKernelGGL(p2m_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, f, M);
   else hipLaunchKernelGGL(p2m_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, f, M);
 }
-void launch_m2m(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *M,
-                hipStream_t s) {
+void launch_m2m(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int child_base, int nrhs,
+                double *M, hipStream_t s) {
   if (nbox <= 0) return;
   dim3 grid((nbox + 15) / 16, nrhs);
-  if (t.KP == 16) hipLaunchKernelGGL(m2m_mfma_kernel<16>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
-  else if (t.KP == 32) hipLaunchKernelGGL(m2m_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
-  else hipLaunchKernelGGL(m2m_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, boxes, nbox, M);
+  if (t.KP == 16) hipLaunchKernelGGL(m2m_mfma_kernel<16>, grid, dim3(256), 0, s, t, g, boxes, nbox, child_base, M);
+  else if (t.KP == 32) hipLaunchKernelGGL(m2m_mfma_kernel<32>, grid, dim3(256), 0, s, t, g, boxes, nbox, child_base, M);
+  else hipLaunchKernelGGL(m2m_mfma_kernel<48>, grid, dim3(256), 0, s, t, g, boxes, nbox, child_base, M);
 }
 void launch_m2m2(const DevTables &t, const DevTree &g, const int *boxes, int nbox, int nrhs, double *M,
                  hipStream_t s) {
