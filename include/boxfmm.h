@@ -262,6 +262,21 @@ int bx_interpolate(const bx_ctx *ctx, const bx_tree *tree, const double *V, cons
  * timed evaluations to *n_evals and clears the record.  Recording adds a few
  * microseconds per phase.  Errors: BX_E_ARG, BX_E_HIP.
  */
+/*
+ * Copy one box's expansion from the last evaluation to the host (synchronizes
+ * `stream`).  which 0: the multipole phi(z) = a_0 log(z - c) + sum_k a_k
+ * (z - c)^-k of the sources in the box (the far field of section 3.1, a_0 = the
+ * integral of f~ over the box); 1: the local expansion psi(z) = sum_l b_l
+ * (z - c)^l of the sources far from it; V = Re(phi or psi) / 2 pi; c the box
+ * centre, z = x1 + i x2.  out[2k], out[2k+1] = Re, Im of a_k (or b_k), k = 0..p,
+ * unscaled (the library stores them scaled by powers of the box width).  box:
+ * the library's box index (0 .. n_trees - 1 are the roots); rhs < the n_rhs
+ * of the last evaluation.
+ * Errors: BX_E_ARG (bad box, rhs, which or NULL), BX_E_UNSUPPORTED (no
+ * evaluation yet), BX_E_HIP.
+ */
+int bx_expansion_read(const bx_ctx *ctx, const bx_tree *tree, int which, int64_t box, int rhs, double *out_host,
+                      bx_stream_t stream);
 int bx_profile(bx_ctx *ctx, int enable);
 int bx_profile_read(bx_ctx *ctx, double *ms, int *n_evals);
 

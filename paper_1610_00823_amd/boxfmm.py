@@ -29,7 +29,7 @@ PHASES = ["p2m", "m2m", "m2l", "p2l", "l2l", "leaf"]
 SYMBOLS = ["bx_create", "bx_build_tables", "bx_tree_upload", "bx_volume_eval_grad", "bx_volume_eval",
            "bx_volume_grad", "bx_query", "bx_tree_list", "bx_table_copy", "bx_split_tolerance", "bx_profile",
            "bx_interpolate", "bx_tree_tuning", "bx_tree_tuning_get", "bx_autotune",
-           "bx_profile_read", "bx_mlp_features", "bx_mlp_create", "bx_mlp_set_params", "bx_mlp_forward",
+           "bx_profile_read", "bx_expansion_read", "bx_mlp_features", "bx_mlp_create", "bx_mlp_set_params", "bx_mlp_forward",
            "bx_mlp_grad", "bx_mlp_adam", "bx_mlp_read", "bx_mlp_destroy",
            "bx_tree_destroy", "bx_destroy", "bx_last_error"]
 
@@ -68,6 +68,7 @@ def lib():
         L.bx_interpolate.argtypes = [vp, vp, vp, vp, i32, vp, i64, vp, vp, vp]
         L.bx_split_tolerance.argtypes = [vp, dp]
         L.bx_tree_tuning.argtypes = [vp, vp, vp, vp]
+        L.bx_expansion_read.argtypes = [vp, vp, i32, i64, i32, vp, vp]
         L.bx_tree_tuning_get.argtypes = [vp, vp]
         L.bx_autotune.argtypes = [vp, vp, vp, i32, vp, vp, i32, vp, vp]
         L.bx_profile.argtypes = [vp, i32]
@@ -212,6 +213,14 @@ class Tree:
         """Set scheduling parameters (0, or -1 for fuse, keeps one); results do not change."""
         t = np.array([heavy, f64_weight, m2l_blocks, fuse], np.float64)
         _check(lib().bx_tree_tuning(self.ctx._h, self._h, t.ctypes.data, _stream_ptr(stream)))
+
+    def expansion(self, which: str = "multipole", box: int = 0, rhs: int = 0, stream=None) -> np.ndarray:
+        """Complex coefficients (k = 0..p) of a box's multipole or local expansion
+        from the last evaluation, unscaled, about the box centre."""
+        out = np.zeros(2 * (self.ctx.p + 1))
+        _check(lib().bx_expansion_read(self.ctx._h, self._h, 0 if which == "multipole" else 1, int(box), int(rhs),
+                                       out.ctypes.data, _stream_ptr(stream)))
+        return out[0::2] + 1j * out[1::2]
 
     def lists(self, kind: int) -> np.ndarray:
         cnt = ctypes.c_int64()

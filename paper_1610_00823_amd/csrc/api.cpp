@@ -933,6 +933,30 @@ int bx_autotune(bx_ctx *ctx, bx_tree *tree, const double *f, int nrhs, double *V
   return rc;
 }
 
+int bx_expansion_read(const bx_ctx *ctx, const bx_tree *tree, int which, int64_t box, int rhs, double *out,
+                      bx_stream_t stream) {
+  if (!ctx || !tree || !out || (which != 0 && which != 1) || box < 0 || box >= tree->H.n_boxes || rhs < 0)
+    return fail(BX_E_ARG, "bx_expansion_read: bad argument");
+  if (tree->ctx != ctx) return fail(BX_E_ARG, "bx_expansion_read: tree belongs to another context");
+  if (!tree->M || rhs >= tree->exp_rhs) return fail(BX_E_UNSUPPORTED, "bx_expansion_read: no evaluation with this rhs");
+  const int KP = ctx->T.KP, nt = ctx->p + 1;
+  std::vector<double> v((size_t)2 * KP);
+  const double *src = (which == 0 ? tree->M : tree->L) + ((size_t)rhs * tree->H.n_boxes + box) * KP * 2;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(v.data(), src, v.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "bx_expansion_read");
+  // stored: multipole a_k / h^k, local b_l h^l (h = the box width)
+  const double h = tree->H.width * std::ldexp(1.0, -tree->H.lvl[box]);
+  double sc = 1.0;
+  for (int k = 0; k < nt; ++k) {
+    out[2 * k] = v[2 * k] * sc;
+    out[2 * k + 1] = v[2 * k + 1] * sc;
+    sc = which == 0 ? sc * h : sc / h;
+  }
+  return BX_OK;
+}
+
 int bx_split_tolerance(bx_ctx *ctx, double tol) {
   if (!ctx || !(tol > 0.0) || tol >= 1.0) return fail(BX_E_ARG, "bx_split_tolerance: need 0 < tol < 1");
   ctx->split_tol = tol;

@@ -502,3 +502,31 @@ def test_power_of_two_scaling_is_exact(ctx8, flags):
         V, G = B.volume_eval_grad(ctx, tr, torch.from_numpy(np.ldexp(f, k)).cuda())
         assert torch.equal(V, V0 * 2.0 ** k), k          # 2.0 ** k is exact
         assert torch.equal(G, G0 * 2.0 ** k), k
+
+
+# ------------------------------------------------ expansions: Gauss law
+@pytest.mark.parametrize("flags", [B.BX_FP64, B.BX_SPLIT_INT8], ids=["fp64", "split"])
+def test_root_multipole_gauss_law_and_exterior(ctx8, flags):
+    # P2M and M2M on the GPU end to end: the root's a_0 is the total source
+    # integral of f~ (the oracle's exact per-leaf integrals), and the root
+    # multipole reproduces the oracle's potential on circles of radius 2 and
+    # 5 about the root centre (truncation (0.71 / R)^31, below 1e-13 there).
+    torch = _torch()
+    ctx = ctx8 if flags == B.BX_FP64 else B.Context(8, 30, flags)
+    t = I.point_refined_tree([[0.3, 0.2], [-0.26, -0.4], [0.1, 0.35]], [6, 4, 5])
+    f = I.sample(t, I.random_gaussians(12, 6, log_sigma=(0.02, 0.2)), 8)
+    tr = B.Tree.from_inputs(ctx, t)
+    B.volume_eval_grad(ctx, tr, torch.from_numpy(f).cuda())
+    a = tr.expansion("multipole", 0)
+    Q = oracle.leaf_mass(t.level, f, t.width).sum()
+    print(f"a_0 = {a[0].real:.15e}, integral of f~ = {Q:.15e}")
+    assert abs(a[0] - Q) <= 1e-13 * np.abs(f).max() * t.width ** 2
+    th = np.linspace(0, 2 * np.pi, 24, endpoint=False)
+    for R in (2.0, 5.0):
+        zt = t.cx + 1j * t.cy + R * np.exp(1j * th)
+        w = zt - (t.cx + 1j * t.cy)
+        phi = a[0] * np.log(w) + sum(a[k] * w ** (-k) for k in range(1, len(a)))
+        Vo, _, _ = oracle.volume(t.level, t.ix, t.iy, f, zt.real, zt.imag)
+        e = np.abs(phi.real / (2 * np.pi) - Vo).max() / np.abs(Vo).max()
+        print(f"R = {R}: multipole vs oracle {e:.2e}")
+        assert e < 1e-12
