@@ -433,3 +433,19 @@ def test_tuning_parameters_host_side():
     assert tr.tuning() == (1.0, 16.0, 4096, 0)
     rc = B.lib().bx_autotune(ctx._h, tr._h, None, 1, None, None, 1, None, None)
     assert rc == B.BX_E_ARG
+
+
+def test_expansion_read_errors():
+    # Reading a box's expansion needs an evaluation (none on a host-only context)
+    # and a valid box, kind and right-hand side.
+    ctx = B.Context(8, 16, B.BX_FP64 | B.BX_HOST_ONLY)
+    tr = B.Tree.from_inputs(ctx, I.uniform_tree(2))
+    with pytest.raises(B.BoxFMMError) as e:
+        tr.expansion("multipole", 0)
+    assert e.value.code == B.BX_E_UNSUPPORTED
+    for box in (-1, int(tr.query("n_boxes"))):
+        with pytest.raises(B.BoxFMMError) as e:
+            tr.expansion("local", box)
+        assert e.value.code == B.BX_E_ARG
+    out = np.zeros(34)
+    assert B.lib().bx_expansion_read(ctx._h, tr._h, 2, 0, 0, out.ctypes.data, None) == B.BX_E_ARG
