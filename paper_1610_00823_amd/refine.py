@@ -197,8 +197,12 @@ def build_trees(funs, propose, n: int = 8, tol: float = 1e-10, cap: int = 12, cx
         st.failed_leaves += int(bad.sum())     # the plain criterion splits these further
         keep = [a[~bad] for a in pl]
         if bad.any():
+            # the check already decided that these leaves split: the plain method
+            # continues from their children
             t0 = time.perf_counter()
-            fb = I.adaptive_tree(funs[s], n, tol, cap, cx=cx, cy=cy, width=width, roots=tuple(a[bad] for a in pl))
+            kids = (np.repeat(pl[0][bad] + 1, 4), (2 * pl[1][bad][:, None] + cxx).ravel(),
+                    (2 * pl[2][bad][:, None] + cyy).ravel())
+            fb = I.adaptive_tree(funs[s], n, tol, cap, cx=cx, cy=cy, width=width, roots=kids)
             T["fallback"] += time.perf_counter() - t0
             st.fallback_f_evals += fb.meta["f_evals"]
             keep = [np.concatenate([k_, f_]) for k_, f_ in zip(keep, fb.meta["leaves"])]
