@@ -148,14 +148,18 @@ def trained():
     ref = R.LearnedRefiner(seed=0)
     x = ref.features(s, lv)
     del s
+    torch = _torch()
+    loss0 = ref.loss(x, torch.from_numpy(y).cuda())            # the untrained network
     losses = ref.train(x, y, epochs=8, batch=1024, lr=2e-3, seed=0, log=print)
-    return ref, losses, x, y, lv
+    return ref, [loss0] + losses, x, y, lv
 
 
 def test_training_reduces_the_loss(trained):
     ref, losses, x, y, lv = trained
-    print("loss per epoch:", [round(l_, 4) for l_ in losses])
-    assert min(losses) < 0.7 * losses[0]
+    # (the sums of the gradient use FP32 atomics, so the losses vary a little
+    # from run to run)
+    print("loss before training and per epoch:", [round(l_, 4) for l_ in losses])
+    assert min(losses[1:]) < 0.5 * losses[0]
     pred = ref.predict(x)
     live = lv < CAP                                  # cap-level boxes are never split
     acc = (pred[live] == (y[live] > 0.5)).mean()
