@@ -530,3 +530,29 @@ def test_root_multipole_gauss_law_and_exterior(ctx8, flags):
         e = np.abs(phi.real / (2 * np.pi) - Vo).max() / np.abs(Vo).max()
         print(f"R = {R}: multipole vs oracle {e:.2e}")
         assert e < 1e-12
+
+
+# ------------------------------------------- root boxes away from the origin
+@pytest.mark.parametrize("flags", [B.BX_FP64, B.BX_SPLIT_INT8], ids=["fp64", "split"])
+@pytest.mark.parametrize("cx,cy,width", [(2.5, -1.75, 0.3), (-40.0, 13.0, 7.0)])
+def test_translated_and_scaled_root(ctx8, flags, cx, cy, width):
+    # The same leaves and samples on a root box of centre (cx, cy) and width w:
+    # against the oracle at every node, and against the unit box's result by the
+    # change of variables y = c + w y' (G(w r) = G(r) + log(w) / 2 pi):
+    # V_w = w^2 (V_1 + log(w) Q_1 / 2 pi), grad V_w = w grad V_1, Q_1 = the
+    # integral of f~ over the unit box.
+    import dataclasses
+    torch = _torch()
+    ctx = ctx8 if flags == B.BX_FP64 else B.Context(8, 30, flags)
+    tol = TOL if flags == B.BX_FP64 else SPLIT_TOL
+    t1 = I.point_refined_tree([[0.3, 0.2], [-0.26, -0.4], [0.45, -0.45]], [5, 4, 3])
+    tw = dataclasses.replace(t1, cx=cx, cy=cy, width=width)
+    f = np.random.default_rng(int(width * 10)).standard_normal((t1.n_leaves, 8, 8))
+    Vw, Gw, _ = gpu_eval(ctx, tw, f)
+    V1, G1, _ = gpu_eval(ctx, t1, f)
+    check_vs_oracle(tw, f, Vw[0], Gw[0], tol=tol)
+    Q1 = oracle.leaf_mass(t1.level, f, 1.0).sum()
+    Vlaw = width ** 2 * (V1[0] + np.log(width) * Q1 / (2 * np.pi))
+    ev, eg = E(Vw[0], Vlaw), E(Gw[0], width * G1[0])
+    print(f"root ({cx}, {cy}) width {width}: change of variables E(V)={ev:.2e} E(G)={eg:.2e}")
+    assert ev < tol and eg < tol
