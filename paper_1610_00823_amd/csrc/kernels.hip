@@ -805,35 +805,40 @@ __global__ void __launch_bounds__(256) split_prep_kernel(const double *__restric
   }
 }
 
-// Near (U list) field of one 64-leaf tile in int8 slices; writes V and G (the
-// FP64 leaf kernel then adds L2T and the W list).  Block = 8 waves: wave
-// (w4, half) owns row tiles mt0 + w4 + 4i (i < TPW) and the 16-column tiles
+// Near (U list) field of one 64-leaf tile in int8 slices, plus L2T and the W
+// list in FP64; writes V and G.  Two blocks of 4 waves share a work unit, one
+// per half of the tile's 64 columns (block b: unit 8 (b / 16) + b % 8, half
+// (b / 8) % 2, so both halves run on the unit's XCD), and two blocks fit on a
+// CU, so one block's index loads and epilogue overlap the other's products.
+// Wave w4 owns row tiles mt0 + w4 + 4i (i < TPW) and the 16-column tiles
 // 2 half, 2 half + 1.  Per work item (slot, 64-wide K chunk) the B slices of
-// the 64 columns are staged in LDS (double buffered, swizzled so that the
-// 16-lane groups of a 16-byte read hit distinct banks); the A slices stream
+// the block's 32 columns are staged in LDS (double buffered, swizzled so that
+// the 16-lane groups of a 16-byte read hit distinct banks); the A slices stream
 // from the table two iterations ahead, in the slice order 0,5,1,4,2,3 that
 // alternates long and short iterations.
 template <int TPW, int NCH, int KCF>
-__global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTree g, const int8_t *__restrict__ fsl,
+__global__ void __launch_bounds__(256, 2) leaf_near_i8_kernel(DevTables t, DevTree g, const int8_t *__restrict__ fsl,
                                                              const double *__restrict__ lmass,
                                                              const double *__restrict__ fscale,
                                                              const double *__restrict__ f,
                                                              const double *__restrict__ M,
                                                              const double *__restrict__ L, double *__restrict__ V,
                                                              double *__restrict__ G) {
-  constexpr int SG = NEAR_SG, P = 64 * NCH, MTR = 3 * P / 16, PPT = SG * 256 / 512;
+  constexpr int HC = LEAF_TILE / 2;                        // columns per block
+  constexpr int SG = NEAR_SG, P = 64 * NCH, MTR = 3 * P / 16, PPT = SG * HC * 4 / 256;
   constexpr int KSC = KCF / 4, PERT = KCF / 8, SBF = KCF + 1;   // FP64 phase: chunks of KCF columns
-  constexpr int BYTES_I8 = 2 * SG * 256 * 16, BYTES_F64 = 2 * LEAF_TILE * SBF * 8;
+  constexpr int BYTES_I8 = 2 * SG * HC * 4 * 16, BYTES_F64 = 2 * HC * SBF * 8;
+  static_assert(SG * HC * 4 % 256 == 0, "staging pieces must divide over the block");
   __shared__ __attribute__((aligned(16))) unsigned char smem[BYTES_I8 > BYTES_F64 ? BYTES_I8 : BYTES_F64];
   __shared__ double sMass[64];
-  uint4(*sB)[SG * 256] = (uint4(*)[SG * 256])smem;
-  const int tile = g.nunit_tile[blockIdx.x];
+  uint4(*sB)[SG * HC * 4] = (uint4(*)[SG * HC * 4])smem;  // [buf][slice][local column][16-byte piece]
+  const int unit = (blockIdx.x >> 4) * 8 + (blockIdx.x & 7), half = (blockIdx.x >> 3) & 1;
+  const int tile = g.nunit_tile[unit];
   if (tile < 0) return;                                    // whole block: no barrier is skipped
-  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), w4 = wave & 3,
-            half = wave >> 2;
+  const int tid = threadIdx.x, lane = tid & 63, w4 = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col = lane & 15, kq = lane >> 4, rhs = blockIdx.z;
-  const int mt0 = g.nunit_mt[blockIdx.x] & 0xffff;         // first row tile of this unit
-  const int ni = g.nunit_mt[blockIdx.x] >> 16;             // row tiles per wave: TPW, or 1 for a heavy tile's thirds
+  const int mt0 = g.nunit_mt[unit] & 0xffff;               // first row tile of this unit
+  const int ni = g.nunit_mt[unit] >> 16;                   // row tiles per wave: TPW, or 1 for a heavy tile's thirds
   const int NL = g.n_leaves, Sf = g.split_sf;
   const int s0 = g.nslot_ptr[tile], s1 = g.nslot_ptr[tile + 1], nitems = (s1 - s0) * NCH;
   const int nsl = g.tile_nsl[tile], Sv = nsl & 255, Sd = (nsl >> 8) & 255;
@@ -851,7 +856,7 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
   // the tile's slot configurations and source leaves (at most 33 slots) in LDS:
   // index reads in the loop then never wait behind the vector-memory queue
   __shared__ int sCfg[33], sSrc[33 * 64];
-  for (int i = tid; i < (s1 - s0) * 64; i += 512) sSrc[i] = g.nslot_src[(size_t)s0 * 64 + i];
+  for (int i = tid; i < (s1 - s0) * 64; i += 256) sSrc[i] = g.nslot_src[(size_t)s0 * 64 + i];
   if (tid < s1 - s0) sCfg[tid] = g.nslot_cfg[s0 + tid];
   __syncthreads();
 
@@ -864,16 +869,17 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
       for (int d = 0; d < SG; ++d) acc[i][nt][d] = i32x4{0, 0, 0, 0};
   double mU = 0.0;
 
-  // staging of item j (slot s0 + j / NCH, chunk j % NCH): piece q = tid + 512 m
-  // is 16 bytes (k 16 kq'..) of slice b of column c'
+  // staging of item j (slot s0 + j / NCH, chunk j % NCH): piece q = tid + 256 m
+  // is 16 bytes (k 16 kk..) of slice b of local column lc (tile column
+  // HC half + lc)
   uint4 stg[PPT];
   bool sok[PPT];
   auto stage_load = [&](int j) {
     const int sl = j / NCH, ch = j % NCH;
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-      const int q = tid + 512 * m, b = q >> 8, c = (q >> 2) & 63, kk = q & 3;
-      const int src = sSrc[sl * 64 + c];
+      const int q = tid + 256 * m, b = q >> 7, lc = (q >> 2) & (HC - 1), kk = q & 3;
+      const int src = sSrc[sl * 64 + HC * half + lc];
       sok[m] = src >= 0;
       const int bb = b < Sf ? b : Sf - 1;
       stg[m] = *(const uint4 *)(fr + ((size_t)bb * NL + (src >= 0 ? src : 0)) * P + ch * 64 + kk * 16);
@@ -882,8 +888,8 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
   auto stage_write = [&](int buf) {
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-      const int q = tid + 512 * m, b = q >> 8, c = (q >> 2) & 63, kk = q & 3;
-      sB[buf][b * 256 + c * 4 + (kk ^ ((c >> 2) & 3))] = sok[m] ? stg[m] : make_uint4(0, 0, 0, 0);
+      const int q = tid + 256 * m, b = q >> 7, lc = (q >> 2) & (HC - 1), kk = q & 3;
+      sB[buf][b * HC * 4 + lc * 4 + (kk ^ ((lc >> 2) & 3))] = sok[m] ? stg[m] : make_uint4(0, 0, 0, 0);
     }
   };
   // A fragments: a_cur for this iteration, a_nxt for the next, a_new two ahead
@@ -935,8 +941,8 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
           i32x4 bv[2];
 #pragma unroll
           for (int nt = 0; nt < 2; ++nt) {
-            const int c = (2 * half + nt) * 16 + col;
-            bv[nt] = __builtin_bit_cast(i32x4, S[b * 256 + c * 4 + (kq ^ ((c >> 2) & 3))]);
+            const int lc = nt * 16 + col;
+            bv[nt] = __builtin_bit_cast(i32x4, S[b * HC * 4 + lc * 4 + (kq ^ ((lc >> 2) & 3))]);
           }
 #pragma unroll
           for (int i = 0; i < NI; ++i)
@@ -996,8 +1002,8 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
         fa[i][nt][r] = v;
       }
   }
-  double *sF = (double *)smem;                             // [2][64 * SBF]
-  const int scol = tid >> 3, sq = tid & 7;                 // staging: 8 threads per column
+  double *sF = (double *)smem;                             // [2][HC * SBF], local columns
+  const int lcol = tid >> 3, scol = HC * half + lcol, sq = tid & 7;   // staging: 8 threads per column
   const int stgt = g.tile_tgt[tile * LEAF_TILE + scol];
   const double sh = stgt >= 0 ? box_h(g.width, g.leaf_level[stgt]) : 1.0;
   const double sinv_h2 = stgt >= 0 ? 1.0 / (sh * sh) : 0.0;
@@ -1045,7 +1051,7 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
     const int NC = (slot_type[sl] == 0 ? P : K2) / KCF;
     {
       const double *mw = leaf_mass + (size_t)slot_op[sl] * kmax + c * KCF + sq * PERT;
-      double *dst = sF + buf * LEAF_TILE * SBF + scol * SBF + sq * PERT;
+      double *dst = sF + buf * HC * SBF + lcol * SBF + sq * PERT;
 #pragma unroll
       for (int j = 0; j < PERT; ++j) {
         dst[j] = rb.v[j];
@@ -1061,7 +1067,7 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
     const double *An = more ? f64_a(nsl, nc) : Ac;
     const size_t stn = more ? f64_stride(nsl) : stc;
     if (more) f64_b(nsl, nc);
-    const double *Sx = sF + buf * LEAF_TILE * SBF;
+    const double *Sx = sF + buf * HC * SBF;
 #pragma unroll
     for (int ks = 0; ks < KSC; ++ks) {
       double a[TPW];
@@ -1076,7 +1082,7 @@ __global__ void __launch_bounds__(512, 1) leaf_near_i8_kernel(DevTables t, DevTr
       }
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt) {
-        const double b = Sx[((2 * half + nt) * 16 + col) * SBF + kq * KSC + ks];
+        const double b = Sx[(nt * 16 + col) * SBF + kq * KSC + ks];
 #pragma unroll
         for (int i = 0; i < TPW; ++i)
           if (i < ni) fa[i][nt] = mfma4(a[i], b, fa[i][nt]);
@@ -1304,9 +1310,10 @@ void launch_leaf_split(const DevTables &t, const DevTree &g, const int8_t *fsl, 
                        const double *fscale, const double *f, int nrhs, const double *M, const double *L, double *V,
                        double *G, hipStream_t s) {
   if (g.n_nunits <= 0) return;
-  const dim3 grid(g.n_nunits, 1, nrhs);
+  // two half-tile blocks per unit (the unit list is padded to a multiple of 8)
+  const dim3 grid(2 * g.n_nunits, 1, nrhs);
 #define BX_NEAR(NCH, KCF)                                                                                        \
-  hipLaunchKernelGGL((leaf_near_i8_kernel<3, NCH, KCF>), grid, dim3(512), 0, s, t, g, fsl, lmass, fscale, f, M, L, \
+  hipLaunchKernelGGL((leaf_near_i8_kernel<3, NCH, KCF>), grid, dim3(256), 0, s, t, g, fsl, lmass, fscale, f, M, L, \
                      V, G)
   if (t.n == 8 && t.leaf_kc == 64) BX_NEAR(1, 64);
   else if (t.n == 8) BX_NEAR(1, 32);
