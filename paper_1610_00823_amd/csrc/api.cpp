@@ -320,6 +320,8 @@ static int upload_units(bx_ctx *ctx, bx_tree *t, hipStream_t s) {
       }
     }
     order_units(nu, nunit_tile, nunit_mt);
+    // the int8 kernel maps block b to unit 8 (b / 16) + b % 8 of a list padded to whole rows of 8
+    if (nunit_tile.size() % 8 != 0) return fail(BX_E_ARG, "upload_units: unit list not padded to 8");
   }
   // upload the new lists first; the old ones stay in use until all copies succeeded
   std::vector<void *> bufs;
