@@ -830,7 +830,7 @@ __global__ void __launch_bounds__(256, 2) leaf_near_i8_kernel(DevTables t, DevTr
   constexpr int BYTES_I8 = 2 * SG * HC * 4 * 16, BYTES_F64 = 2 * HC * SBF * 8;
   static_assert(SG * HC * 4 % 256 == 0, "staging pieces must divide over the block");
   __shared__ __attribute__((aligned(16))) unsigned char smem[BYTES_I8 > BYTES_F64 ? BYTES_I8 : BYTES_F64];
-  __shared__ double sMass[64];
+  __shared__ double sMass[HC];                            // per local column
   uint4(*sB)[SG * HC * 4] = (uint4(*)[SG * HC * 4])smem;  // [buf][slice][local column][16-byte piece]
   const int unit = (blockIdx.x >> 4) * 8 + (blockIdx.x & 7), half = (blockIdx.x >> 3) & 1;
   const int tile = g.nunit_tile[unit];
@@ -867,7 +867,6 @@ __global__ void __launch_bounds__(256, 2) leaf_near_i8_kernel(DevTables t, DevTr
     for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
       for (int d = 0; d < SG; ++d) acc[i][nt][d] = i32x4{0, 0, 0, 0};
-  double mU = 0.0;
 
   // staging of item j (slot s0 + j / NCH, chunk j % NCH): piece q = tid + 256 m
   // is 16 bytes (k 16 kk..) of slice b of local column lc (tile column
@@ -975,11 +974,16 @@ __global__ void __launch_bounds__(256, 2) leaf_near_i8_kernel(DevTables t, DevTr
   }
 #undef BX_RUN1
 #undef BX_RUN
-  if (tid < 64)                                            // mass weights of the sources of column tid
-    for (int sl = 0; sl < s1 - s0; ++sl) {
-      const int src = sSrc[sl * 64 + tid];
-      if (src >= 0) mU = fma(t.split_cfg_w2[sCfg[sl]], lmass[(size_t)rhs * NL + src], mU);
-    }
+  // U-list mass of column HC half + tid / 8: this thread's slots tid % 8 + 8 k
+  // (at most 33 slots), all requested at once; summed over the column's 8
+  // threads together with the FP64 slots' part below
+  double mU = 0.0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const int sl = (tid & 7) + 8 * k;
+    const int src = sl < s1 - s0 ? sSrc[sl * 64 + HC * half + (tid >> 3)] : -1;
+    if (src >= 0) mU = fma(t.split_cfg_w2[sCfg[sl]], lmass[(size_t)rhs * NL + src], mU);
+  }
   // ---- FP64 phase: L2T, the W list and the U slots of tiles left in FP64,
   // seeded with the scaled int8 group sums.  The FP64 tables' rows are permuted
   // so that accumulator register r of a lane holds row 4 (lane / 16) + r, the
@@ -1013,7 +1017,7 @@ __global__ void __launch_bounds__(256, 2) leaf_near_i8_kernel(DevTables t, DevTr
   const double *Lr = L + (size_t)rhs * g.n_boxes * K2, *Mr = M + (size_t)rhs * g.n_boxes * K2;
   const double *leaf_frag = t.leaf_frag, *leaf_mass = t.leaf_mass;
   const int kmax = t.leaf_kmax;
-  double mpart = 0.0;
+  double mpart = mU;
   Regs<PERT> rb;
   int ir[TPW];                                             // row tile offset of fragment i (tile 0 for i >= ni)
 #pragma unroll
@@ -1092,14 +1096,11 @@ __global__ void __launch_bounds__(256, 2) leaf_near_i8_kernel(DevTables t, DevTr
     c = nc;
     buf ^= 1;
   }
-  // mass per column: the U part (threads < 64) plus the FP64 slots' part
+  // mass per column: the sum over the column's 8 threads (U and FP64 slots)
   mpart += __shfl_xor(mpart, 1);
   mpart += __shfl_xor(mpart, 2);
   mpart += __shfl_xor(mpart, 4);
-  __syncthreads();
-  if (tid < 64) sMass[tid] = mU;
-  __syncthreads();
-  if (sq == 0) sMass[scol] += mpart;
+  if (sq == 0) sMass[lcol] = mpart;
   __syncthreads();
 #pragma unroll
   for (int nt = 0; nt < 2; ++nt) {
@@ -1107,7 +1108,7 @@ __global__ void __launch_bounds__(256, 2) leaf_near_i8_kernel(DevTables t, DevTr
     const int tgt = g.tile_tgt[tile * LEAF_TILE + cc];
     if (tgt < 0) continue;
     const double h = box_h(g.width, g.leaf_level[tgt]);
-    const double lg = h * h * log(h) * kInv2Pi * sMass[cc];
+    const double lg = h * h * log(h) * kInv2Pi * sMass[nt * 16 + col];
     double *Vt = V + ((size_t)rhs * NL + tgt) * P;
     double *Gt = G + ((size_t)rhs * NL + tgt) * 2 * P;
 #pragma unroll
