@@ -1009,7 +1009,14 @@ __global__ void __launch_bounds__(256, 2) leaf_near_i8_kernel(DevTables t, DevTr
   double *sF = (double *)smem;                             // [2][HC * SBF], local columns
   const int lcol = tid >> 3, scol = HC * half + lcol, sq = tid & 7;   // staging: 8 threads per column
   const int stgt = g.tile_tgt[tile * LEAF_TILE + scol];
+  // the epilogue's targets (columns 16 (2 half + nt) + col) and their levels,
+  // requested beside the staging target's
+  int etgt[2], elev[2];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) etgt[nt] = g.tile_tgt[tile * LEAF_TILE + (2 * half + nt) * 16 + col];
   const double sh = stgt >= 0 ? box_h(g.width, g.leaf_level[stgt]) : 1.0;
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) elev[nt] = g.leaf_level[etgt[nt] >= 0 ? etgt[nt] : 0];
   const double sinv_h2 = stgt >= 0 ? 1.0 / (sh * sh) : 0.0;
   const int f0 = g.tile_ptr[tile], f1 = g.tile_ptr[tile + 1], K2 = 2 * t.KP;
   const int *slot_type = g.slot_type, *slot_op = g.slot_op, *slot_aoff = g.slot_aoff, *slot_src = g.slot_src + scol;
@@ -1104,10 +1111,9 @@ __global__ void __launch_bounds__(256, 2) leaf_near_i8_kernel(DevTables t, DevTr
   __syncthreads();
 #pragma unroll
   for (int nt = 0; nt < 2; ++nt) {
-    const int cc = (2 * half + nt) * 16 + col;
-    const int tgt = g.tile_tgt[tile * LEAF_TILE + cc];
+    const int tgt = etgt[nt];
     if (tgt < 0) continue;
-    const double h = box_h(g.width, g.leaf_level[tgt]);
+    const double h = box_h(g.width, elev[nt]);
     const double lg = h * h * log(h) * kInv2Pi * sMass[nt * 16 + col];
     double *Vt = V + ((size_t)rhs * NL + tgt) * P;
     double *Gt = G + ((size_t)rhs * NL + tgt) * 2 * P;
