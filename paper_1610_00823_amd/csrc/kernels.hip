@@ -767,6 +767,11 @@ __global__ void __launch_bounds__(256) split_prep_kernel(const double *__restric
                                                          int nparts, int Sf, double *__restrict__ fscale,
                                                          int8_t *__restrict__ fsl, double *__restrict__ lmass) {
   const int rhs = blockIdx.y, tid = threadIdx.x;
+  const int lpb = P >= 256 ? 1 : 256 / P;
+  const int leaf = blockIdx.x * lpb + tid / P, k = tid % P;
+  const bool ok = leaf < n_leaves && tid < lpb * P;
+  // this thread's sample and weight, requested together with the partial maxima
+  const double x = ok ? f[((size_t)rhs * n_leaves + leaf) * P + k] : 0.0, wk = ok ? wq[k] : 0.0;
   __shared__ double sm[4];
   double m = 0.0;
   for (int i = tid; i < nparts; i += 256) m = fmax(m, part[(size_t)rhs * nparts + i]);
@@ -780,12 +785,7 @@ __global__ void __launch_bounds__(256) split_prep_kernel(const double *__restric
   if (fr * 128.0 >= 127.5) ++e;
   const double inv = m > 0.0 ? ldexp(1.0, -e) : 0.0;
   if (blockIdx.x == 0 && tid == 0) fscale[rhs] = m > 0.0 ? ldexp(1.0, e) : 1.0;
-  const int lpb = P >= 256 ? 1 : 256 / P;
-  const int leaf = blockIdx.x * lpb + tid / P, k = tid % P;
-  const bool ok = leaf < n_leaves && tid < lpb * P;
-  double x = 0.0;
   if (ok) {
-    x = f[((size_t)rhs * n_leaves + leaf) * P + k];
     double v = x * inv;
     for (int b = 0; b < Sf; ++b) {
       const double sc = v * 128.0, t = rint(sc);
@@ -794,7 +794,7 @@ __global__ void __launch_bounds__(256) split_prep_kernel(const double *__restric
     }
   }
   // per-leaf mass: P = 64 -> one wave per leaf; P = 256 -> four waves
-  double w = ok ? wq[k] * x : 0.0;
+  double w = ok ? wk * x : 0.0;
   for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
   if (P <= 64) {
     if ((tid & 63) == 0 && ok) lmass[(size_t)rhs * n_leaves + leaf] = w;
